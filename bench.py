@@ -1,0 +1,210 @@
+"""Benchmark: mixed-precision nested recursive Cholesky factor + FP64-refined
+solve on one MI355X.
+
+A step is the whole hot path on one synthetic system: Tree-POTRF with
+Tree-TRSM / Tree-SYRK (FP16 levels 0-1, FP32 levels 2-5, FP64 leaves of 256)
+of the 16384 x 16384 dominance-ratio-1.5 SPD matrix, then the substitution
+solve and FP64-residual iterative refinement of one right-hand side to
+||d||_inf <= 1e-13 ||x||_inf.  value = effective TFLOP/s = (n^3/3) / time to
+solution.  Inputs are generated in device memory before the timed region.
+
+Prints ONE JSON line (rank 0).  Extra fields: the same step on the all-FP64
+tree (time-to-solution speedup), factor-only rate, the roofline of the
+dominant kernel measured with HIP events inside the timed region, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"gemm_e4m3": 5000.0, "gemm_f16": 2500.0, "gemm_f32": 157.3, "gemm_f64": 78.6}
+HBM_GBS = 8000.0
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(n_full: int, ratio: float, offdiag, leaf: int, budget_s: float) -> dict:
+    """The CPU oracle (factor + refined solve) on a bounded sample: the same
+    generator, ratio and tree at a smaller n chosen to take ~budget_s."""
+    import oracle as O
+    from paper_2601_08082_amd import spdgen
+
+    def run(n):
+        A = spdgen.gen_spd(n, ratio, 0.0, seed=8)
+        B = spdgen.gen_rhs(n, 1, seed=108)
+        t0 = time.perf_counter()
+        L, st, _ = O.factor(A, tree=O.Tree(leaf=leaf, offdiag=list(offdiag)))
+        X, st2, it, _ = O.solve(L, B, A=A, tol=1e-13, max_iter=20)
+        dt = time.perf_counter() - t0
+        assert st == O.OK and st2 == O.OK
+        return dt
+
+    n0 = 1024
+    t0 = run(n0)
+    n = int((budget_s / max(t0, 1e-3)) ** (1.0 / 3.0) * n0) // 256 * 256
+    n = max(n0, min(n, n_full))
+    t = run(n) if n != n0 else t0
+    return {"value": (n ** 3 / 3) / t / 1e12, "unit": "TFLOP/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle factor + refined solve at n={n} (same generator, ratio, tree), "
+                      f"{t:.1f} s on {_cpu_model()}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--ratio", type=float, default=1.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the single-matrix path is not sharded "
+              "across GPUs in this build (see the design notes on sharding)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2601_08082_amd import mpchol as M
+    from paper_2601_08082_amd import spdgen, spdgen_gpu
+
+    n, ratio = args.n, args.ratio
+    leaf = 256
+    mixed_levels = [M.F16, M.F16, M.F32, M.F32, M.F32, M.F32]
+    tree = M.Tree(leaf=leaf, offdiag=mixed_levels, leaf_prec=M.F64)
+    tree64 = M.Tree(leaf=leaf, offdiag=[M.F64], leaf_prec=M.F64)
+    flops = n ** 3 / 3.0
+
+    ctx = M.Context(0)
+    A = spdgen_gpu.gen_spd(n, ratio, 0.0, seed=8, lda=n)
+    B = spdgen_gpu.gen_rhs(n, 1, seed=108, ldb=n)
+    L = torch.empty_like(A)
+    X = torch.empty_like(B)
+    torch.cuda.synchronize()
+
+    def step(tr):
+        _, finfo = ctx.factor(A, n, tr, L_cm=L, sync=False)
+        _, sinfo = ctx.solve(L, B, n, A_cm=A, tol=1e-13, max_iter=20, X_cm=X)
+        return sinfo
+
+    for _ in range(args.warmup):
+        s = step(tree)
+    torch.cuda.synchronize()
+    ctx.profile(["gemm_f16"])
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = step(tree)
+        iters.append(s["ir_iters"])
+        if s["status"] != 0:
+            raise RuntimeError(f"solve failed: {s}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile([])
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    # factor-only rate and info (outside the timed region)
+    _, finfo = ctx.factor(A, n, tree, L_cm=L, sync=True)
+    fms = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ctx.factor(A, n, tree, L_cm=L, sync=False)
+        torch.cuda.synchronize()
+        fms.append((time.perf_counter() - a) * 1e3)
+    factor_ms = float(np.median(fms))
+
+    # solution check: Gershgorin certificate with the FP64 residual (GPU data, CPU arithmetic)
+    s = step(tree)
+    torch.cuda.synchronize()
+    Ah = A.cpu().numpy()
+    x = X.cpu().numpy()[0]
+    b = B.cpu().numpy()[0]
+    r = b - Ah @ x
+    lam = spdgen.gershgorin_lower_bound(n, ratio, 0.0, Ah)
+    cert = float(np.linalg.norm(r) / lam / np.linalg.norm(x))
+    del Ah
+
+    fp64 = None
+    if not args.no_fp64:
+        step(tree64)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        k64 = max(1, min(args.steps, 3))
+        for _ in range(k64):
+            s64 = step(tree64)
+        torch.cuda.synchronize()
+        fp64_ms = (time.perf_counter() - a) * 1e3 / k64
+        fp64 = {"tts_ms": fp64_ms, "ir_iters": s64["ir_iters"],
+                "speedup_mixed_vs_fp64": fp64_ms / ms_step}
+
+    ms16, work16, n16 = prof["gemm_f16"]
+    achieved = (work16 / n16) / (ms16 / n16 * 1e-3) / 1e12 if n16 else 0.0
+    roof = {"bound": "mfma", "kernel": "k_gemm_q<f16> (grouped FP16 GEMM/SYRK)",
+            "achieved": achieved, "peak": PEAK_TFLOPS["gemm_f16"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS["gemm_f16"], "traffic": None,
+            "launches_per_step": n16 / args.steps, "ms_per_step": ms16 / args.steps,
+            "flops_per_launch": work16 / n16 if n16 else 0.0}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, ratio, mixed_levels, leaf, args.cpu_budget)
+
+    stats = M.plan_stats(n, tree)
+    out = {
+        "metric": "effective TFLOP/s (n^3/3) + time-to-solution at 1e-12 rel err vs FP64 path",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16/f32 MFMA (f32 acc) + f64 leaves, f64 in/out",
+        "data": "synthetic",
+        "config": {"workload": f"SPD n={n} dominance ratio {ratio}, tree [F16,F16,F32,F32,F32,F32] "
+                               f"leaf {leaf} FP64, 1 rhs, FP64-residual refinement to 1e-13 correction",
+                   "n": n, "leaf": leaf, "nrhs": 1, "parallelism": "single GPU"},
+        "time_to_solution_ms": ms_step,
+        "factor_ms": factor_ms,
+        "factor_tflops": flops / (factor_ms * 1e-3) / 1e12,
+        "ir_iters": int(np.median(iters)),
+        "solution_error_certificate": cert,
+        "fp64_path": fp64,
+        "plan": {"launches": stats["launches"], "ws_gb": stats["ws_bytes"] / 1e9,
+                 "flop_share": {k: v / flops for k, v in stats["flops"].items()}},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[2]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,219 @@
+/*
+ * mpchol -- nested recursive mixed-precision Cholesky factorization and solve
+ * for AMD MI355X (gfx950).
+ *
+ * The method is that of Carrica, Alomairy, Ringoot and Edelman, "Hierarchical
+ * Recursive Precision for Accelerating Symmetric Linear Solves on MXUs"
+ * (arXiv 2601.08082): Tree-POTRF (Algorithm 1) splits the matrix, and the
+ * off-diagonal work is itself recursive -- Tree-TRSM (Algorithm 2) and
+ * Tree-SYRK (Algorithm 3) -- so that almost all flops are GEMMs.  The GEMMs
+ * issued at recursion depth l run in that level's precision (Section 3.3; a
+ * precision list runs from the outermost level to the innermost, Section 4.2),
+ * each low-precision GEMM operand is scaled into the format's range first and
+ * the product scaled back (Section 3.4).  Leaf factorizations and leaf
+ * triangular solves run in a high precision.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major with a leading dimension (LAPACK style).  Only
+ *     the lower triangle of a symmetric matrix is referenced; the strictly
+ *     upper triangle is never read or written.
+ *   - Matrix and vector pointers are DEVICE pointers owned by the caller.  The
+ *     context owns plans, workspace and device status words.
+ *   - stream is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; entry points that return numeric status synchronize it.
+ *   - Return value: 0 on success; -i when argument i is invalid (nothing is
+ *     enqueued); a positive MPCHOL_* status otherwise.  No exception crosses
+ *     this boundary.
+ *   - A context is not thread-safe: use one per host thread / stream.
+ */
+#ifndef MPCHOL_H
+#define MPCHOL_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPCHOL_ABI_VERSION 1
+#define MPCHOL_MAX_LEVELS 24
+
+/* Operand precisions.  E4M3 is the OCP 8-bit e4m3fn format (max 448). */
+typedef enum {
+  MPCHOL_E4M3 = 0,
+  MPCHOL_F16 = 1,
+  MPCHOL_F32 = 2,
+  MPCHOL_F64 = 3
+} mpchol_prec;
+
+/* Status codes (positive return values and mpchol_info.status). */
+enum {
+  MPCHOL_OK = 0,
+  MPCHOL_NOT_SPD = 1,        /* a pivot was <= 0 or NaN; failed_index is its 1-based column */
+  MPCHOL_NONFINITE = 2,      /* a quantized operand block or the solution held Inf/NaN      */
+  MPCHOL_NOT_CONVERGED = 3,  /* refinement hit max_iter or diverged                         */
+  MPCHOL_HIP_ERROR = 4,      /* a HIP runtime call failed                                    */
+  MPCHOL_NOT_SUPPORTED = 5   /* a descriptor feature this build does not implement          */
+};
+
+/*
+ * Precision-tree descriptor.
+ *   leaf         b >= 1: Tree-POTRF/TRSM/SYRK stop splitting at size <= b
+ *                (Algorithms 1-3).
+ *   split_align  1: n1 = floor(n/2) (the paper's example split, Algorithm 1);
+ *                k > 1: n1 = k*ceil(floor(n/2)/k), clamped to [1, n-1].
+ *   nlevels      number of offdiag entries in use, 1..MPCHOL_MAX_LEVELS.
+ *   offdiag[l]   mpchol_prec of every GEMM of the Tree-TRSM and Tree-SYRK
+ *                issued by a Tree-POTRF node at depth l (root = 0); depths
+ *                >= nlevels use offdiag[nlevels-1].  (int32_t for a fixed size.)
+ *   leaf_prec    MPCHOL_F64 or MPCHOL_F32: leaf POTRF and leaf TRSM.
+ *   syrk_leaf_mode  0: a leaf SYRK runs in its issuing level's precision;
+ *                1: in leaf_prec.
+ *   scale_mode   0: block scale s = 2^e, the smallest power of two with
+ *                max|B| <= Rmax*s, and s >= 1 (Section 3.4 with alpha rounded
+ *                up to a power of two); 1: also scale up (e < 0) for FP16 and
+ *                E4M3 operands.  FP32 operands are never scaled up.
+ *   scale_tile   must be 0 (one scale per GEMM operand block).
+ *   node_prec    NULL, or a HOST array of n_nodes int8 precisions, one per
+ *                internal Tree-POTRF node in preorder (node, then its A11
+ *                subtree, then its A22 subtree); entries < 0 fall back to
+ *                offdiag.  This is how a per-block precision policy is applied.
+ */
+typedef struct {
+  int32_t abi_version;
+  int32_t leaf;
+  int32_t split_align;
+  int32_t nlevels;
+  int32_t offdiag[MPCHOL_MAX_LEVELS];
+  int32_t leaf_prec;
+  int32_t syrk_leaf_mode;
+  int32_t scale_mode;
+  int32_t scale_tile;
+  const int8_t* node_prec;
+  int64_t n_nodes;
+} mpchol_tree;
+
+typedef struct {
+  int32_t status;          /* MPCHOL_* */
+  int32_t ir_iters;        /* refinement iterations performed (solve)            */
+  int64_t failed_index;    /* 1-based column of the first bad pivot, else 0      */
+  double final_rel_corr;   /* max over columns of ||d||_inf / ||x||_inf, last step */
+  double ms_factor;        /* device time of the call, when synchronized         */
+  double ms_solve;
+} mpchol_info;
+
+typedef struct mpchol_ctx_s* mpchol_ctx;
+
+/* Create a context on HIP device `device`.  Returns 0 or MPCHOL_HIP_ERROR. */
+int mpchol_create(mpchol_ctx* ctx, int device);
+/* Release a context and everything it owns (waits for its work to finish). */
+int mpchol_destroy(mpchol_ctx ctx);
+
+/*
+ * Factor A = L L^T (Algorithm 1 with Algorithms 2 and 3 inside).
+ *   n, A, lda   order and lower triangle of the SPD input; lda >= max(1, n).
+ *   L, ldl      output: the lower triangle of L is written (ldl >= max(1, n)).
+ *               L == A with ldl == lda factors in place.  L's strictly upper
+ *               triangle is untouched.
+ *   tree        precision-tree descriptor (above); abi_version must equal
+ *               MPCHOL_ABI_VERSION.
+ *   info        NULL: the call only enqueues.  Otherwise the stream is
+ *               synchronized and info receives status / failed_index /
+ *               ms_factor.
+ * Errors: -2 n < 0; -3 A NULL; -4 lda < max(1,n); -5 L NULL; -6 ldl; -7 bad
+ * descriptor.  After MPCHOL_NOT_SPD the contents of L are unspecified.
+ */
+int mpchol_factor(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
+                  double* L, int64_t ldl, const mpchol_tree* tree,
+                  void* stream, mpchol_info* info);
+
+/*
+ * Solve A X = B with the factor L, then refine with FP64 residuals:
+ *   x0 = L^-T L^-1 b;  repeat r = b - A x (FP64, A's lower triangle),
+ *   d = L^-T L^-1 r, x += d, until max_col ||d||_inf <= tol ||x||_inf, or
+ *   max_iter steps, or the correction grows twice in a row.
+ *   A == NULL: no refinement (plain substitution solve).
+ *   B (n x nrhs, ldb) is not modified; X (n x nrhs, ldx) receives the result.
+ * The stream is synchronized once per refinement step and at the end.
+ * Errors: -2 n < 0; -3 nrhs < 0; -5 lda; -6 L NULL; -7 ldl; -8 B NULL; -9 ldb;
+ * -10 X NULL; -11 ldx; -13 max_iter < 0.
+ */
+int mpchol_solve(mpchol_ctx ctx, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                 const double* L, int64_t ldl, const double* B, int64_t ldb,
+                 double* X, int64_t ldx, double tol, int32_t max_iter,
+                 void* stream, mpchol_info* info);
+
+/*
+ * Factor and solve `batch` independent SPD systems of uneven sizes.
+ *   n_host[i], lda_host[i], ldl_host[i]   host arrays of sizes and strides.
+ *   A_dev[i], L_dev[i], B_dev[i], X_dev[i]  host arrays of device pointers.
+ *   nrhs        right-hand sides per system (B_i, X_i are n_i x nrhs, leading
+ *               dimension n_i).
+ *   tol, max_iter  refinement rule of mpchol_solve, per system.
+ *   tree        descriptor shared by all systems (leaf/split used as given).
+ *   info_host   host array of batch mpchol_info, filled after synchronizing.
+ */
+int mpchol_factor_batched(mpchol_ctx ctx, int64_t batch, const int64_t* n_host,
+                          const double* const* A_dev, const int64_t* lda_host,
+                          double* const* L_dev, const int64_t* ldl_host,
+                          int64_t nrhs, const double* const* B_dev,
+                          double* const* X_dev, double tol, int32_t max_iter,
+                          const mpchol_tree* tree, void* stream, mpchol_info* info_host);
+
+/*
+ * Quantize one operand block the way every low-precision GEMM operand is
+ * quantized (Section 3.4): s = the block scale of max|src| (scale_mode as in
+ * mpchol_tree), then dst[r * ldq + c] = RNE_prec(src(r, c) / s), rounded
+ * directly from FP64 with gradual underflow, and dst[r * ldq + c] = 0 for
+ * cols <= c < ldq.  src is a column-major rows x cols device block (lds);
+ * dst is device memory of rows * ldq elements of the format (FP16: 2 bytes,
+ * E4M3: 1 byte), ldq a multiple of 16 >= cols.  *scale_out (host) receives s.
+ * Synchronizes the stream.  Returns MPCHOL_NONFINITE when src holds Inf/NaN.
+ * Errors: -2 rows; -3 cols; -4 src; -5 lds; -6 prec not FP16/E4M3;
+ * -7 scale_mode; -8 dst; -9 ldq.
+ */
+int mpchol_quantize(mpchol_ctx ctx, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                    int32_t prec, int32_t scale_mode, void* dst, int64_t ldq, double* scale_out,
+                    void* stream);
+
+/*
+ * Host-only introspection of the launch plan for (n, ldl, tree); touches no
+ * device.  flops4[p] receives the GEMM/SYRK flops run in precision p
+ * (indexed by mpchol_prec), leaf_flops the leaf POTRF + TRSM flops,
+ * cast_bytes the algorithmic bytes of the quantize casts (8 B read + the
+ * format's bytes written per element), launches the kernel launches of one
+ * factorization and ws_bytes the quantized-operand workspace.
+ * Errors: -1 n < 0; -2 ldl < max(1,n); -7 bad descriptor.
+ */
+int mpchol_plan_stats(int64_t n, int64_t ldl, const mpchol_tree* tree, double* flops4,
+                      double* leaf_flops, double* cast_bytes, int64_t* launches,
+                      int64_t* ws_bytes);
+
+/*
+ * Per-launch-class device timing (tracing).  Classes: */
+enum {
+  MPCHOL_PROF_GEMM_E4M3 = 0,  /* grouped GEMM / SYRK launches by operand precision */
+  MPCHOL_PROF_GEMM_F16 = 1,
+  MPCHOL_PROF_GEMM_F32 = 2,
+  MPCHOL_PROF_GEMM_F64 = 3,
+  MPCHOL_PROF_CAST = 4,       /* quantize casts            */
+  MPCHOL_PROF_MAXABS = 5,     /* block max-abs reductions  */
+  MPCHOL_PROF_POTRF = 6,      /* leaf POTRF                */
+  MPCHOL_PROF_TRSM = 7,       /* leaf TRSM                 */
+  MPCHOL_PROF_KINDS = 8
+};
+/* mpchol_profile: clear the accumulators and record a HIP event pair around
+ * every later launch whose class bit is set in kind_mask (0 = off).  Events go
+ * on the launch's own stream.  mpchol_profile_read waits for the recorded
+ * events and returns, per class, the summed device milliseconds, the summed
+ * algorithmic work (flops for GEMM/POTRF/TRSM, bytes for cast/max-abs) and the
+ * number of launches.  Arrays have MPCHOL_PROF_KINDS entries (NULL: skip). */
+int mpchol_profile(mpchol_ctx ctx, uint32_t kind_mask);
+int mpchol_profile_read(mpchol_ctx ctx, double* ms, double* work, int64_t* launches);
+
+/* Human-readable build/version string (static storage). */
+const char* mpchol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

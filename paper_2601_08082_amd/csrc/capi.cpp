@@ -1,0 +1,561 @@
+// C-ABI of libmpchol: context, plan cache, executor and the refinement loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mpchol.h"
+#include "internal.h"
+#include "numfmt.h"
+#include "plan.h"
+
+using namespace mpc;
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return MPCHOL_HIP_ERROR; \
+  } while (0)
+
+namespace {
+constexpr int kNormParts = 64;
+constexpr int kMaxRhs = 16;
+}  // namespace
+
+struct mpchol_ctx_s {
+  int device = 0;
+  DevStatus* dst = nullptr;   // device status words
+  DevStatus* hst = nullptr;   // pinned host copy
+  void* ws = nullptr;         // quantized operand copies
+  size_t ws_bytes = 0;
+  double* part = nullptr;     // max-abs partials
+  int64_t part_count = 0;
+  double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
+  int64_t rbuf_count = 0;
+  double* npart = nullptr;    // norm partials (device)
+  double* hnpart = nullptr;   // norm partials (pinned host)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::map<std::string, std::unique_ptr<Plan>> plans;
+  // per-launch-class event timing (mpchol_profile)
+  uint32_t prof_mask = 0;
+  std::vector<hipEvent_t> prof_ev;      // pool, used in pairs
+  std::vector<int> prof_kind;           // kind of each recorded pair
+  std::vector<double> prof_flops;       // algorithmic flops / bytes of each pair
+  size_t prof_used = 0;
+  double acc_ms[MPCHOL_PROF_KINDS] = {0};
+  double acc_work[MPCHOL_PROF_KINDS] = {0};
+  int64_t acc_n[MPCHOL_PROF_KINDS] = {0};
+};
+
+static int launch_kind(const Launch& L) {
+  switch (L.kind) {
+    case Launch::GEMM: return MPCHOL_PROF_GEMM_E4M3 + L.prec;
+    case Launch::CAST: return MPCHOL_PROF_CAST;
+    case Launch::MAXABS: return MPCHOL_PROF_MAXABS;
+    case Launch::POTRF: return MPCHOL_PROF_POTRF;
+    default: return MPCHOL_PROF_TRSM;
+  }
+}
+
+// Record a start event for a launch of `kind` when profiling it; returns the
+// pair index or -1.
+static int prof_begin(mpchol_ctx c, int kind, double work, hipStream_t s) {
+  if (!(c->prof_mask & (1u << kind))) return -1;
+  size_t i = c->prof_used;
+  if (2 * i + 2 > c->prof_ev.size()) {
+    for (int k = 0; k < 2; k++) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->prof_ev.push_back(e);
+    }
+    c->prof_kind.push_back(0);
+    c->prof_flops.push_back(0);
+  }
+  c->prof_kind[i] = kind;
+  c->prof_flops[i] = work;
+  c->prof_used++;
+  if (hipEventRecord(c->prof_ev[2 * i], s) != hipSuccess) return -1;
+  return (int)i;
+}
+static void prof_end(mpchol_ctx c, int i, hipStream_t s) {
+  if (i >= 0) (void)hipEventRecord(c->prof_ev[2 * i + 1], s);
+}
+// Fold the recorded pairs into the accumulators (waits for their events).
+static int prof_collect(mpchol_ctx c) {
+  for (size_t i = 0; i < c->prof_used; i++) {
+    HIPCHK(hipEventSynchronize(c->prof_ev[2 * i + 1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+    int k = c->prof_kind[i];
+    c->acc_ms[k] += ms;
+    c->acc_work[k] += c->prof_flops[i];
+    c->acc_n[k] += 1;
+  }
+  c->prof_used = 0;
+  return 0;
+}
+
+static double launch_work(const Plan& P, const Launch& L) {
+  double w = 0.0;
+  if (L.kind == Launch::GEMM) {
+    for (int i = 0; i < L.count; i++) {
+      const GemmProb& g = P.gemms[L.first + i];
+      w += g.lower ? (double)g.m * (g.m + 1) * g.k : 2.0 * g.m * g.n * g.k;
+    }
+  } else if (L.kind == Launch::CAST) {
+    int esz = L.prec == F16 ? 2 : 1;
+    for (int i = 0; i < L.count; i++) {
+      const CastJob& j = P.casts[L.first + i];
+      w += (double)j.rows * j.cols * (8.0 + esz);
+    }
+  } else if (L.kind == Launch::MAXABS) {
+    for (int i = 0; i < L.count; i++) {
+      const MaxabsJob& j = P.maxabs[L.first + i];
+      w += (double)j.rows * j.cols * 8.0;
+    }
+  } else if (L.kind == Launch::POTRF) {
+    w = (double)L.a1 * L.a1 * L.a1 / 3.0;
+  } else {
+    w = (double)L.a1 * L.a3 * L.a3;
+  }
+  return w;
+}
+
+static void free_plan(Plan& P) {
+  if (P.d_maxabs) (void)hipFree(P.d_maxabs);
+  if (P.d_casts) (void)hipFree(P.d_casts);
+  if (P.d_gemms) (void)hipFree(P.d_gemms);
+  P.d_maxabs = nullptr;
+  P.d_casts = nullptr;
+  P.d_gemms = nullptr;
+}
+
+template <typename T>
+static int upload(T** dptr, const std::vector<T>& v) {
+  if (v.empty()) return 0;
+  HIPCHK(hipMalloc((void**)dptr, sizeof(T) * v.size()));
+  HIPCHK(hipMemcpy(*dptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return 0;
+}
+
+static int ensure_ws(mpchol_ctx c, size_t bytes, int64_t parts) {
+  if (bytes > c->ws_bytes) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->ws) HIPCHK(hipFree(c->ws));
+    c->ws = nullptr;
+    HIPCHK(hipMalloc(&c->ws, bytes));
+    c->ws_bytes = bytes;
+  }
+  if (parts > c->part_count) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->part) HIPCHK(hipFree(c->part));
+    c->part = nullptr;
+    HIPCHK(hipMalloc((void**)&c->part, sizeof(double) * parts));
+    c->part_count = parts;
+  }
+  return 0;
+}
+
+static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, Plan** out) {
+  std::string key = plan_key(n, ldl, t);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) {
+    *out = it->second.get();
+    return 0;
+  }
+  std::unique_ptr<Plan> P(new Plan());
+  build_plan(*P, n, ldl, t);
+  if (upload(&P->d_maxabs, P->maxabs) || upload(&P->d_casts, P->casts) ||
+      upload(&P->d_gemms, P->gemms)) {
+    free_plan(*P);
+    return MPCHOL_HIP_ERROR;
+  }
+  *out = P.get();
+  c->plans[key] = std::move(P);
+  return 0;
+}
+
+static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStream_t s) {
+  const int sm = P.tree.scale_mode;
+  for (const Launch& Lc : P.launches) {
+    hipError_t e = hipSuccess;
+    const int pk = c->prof_mask ? prof_begin(c, launch_kind(Lc), launch_work(P, Lc), s) : -1;
+    switch (Lc.kind) {
+      case Launch::POTRF:
+        e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, s);
+        break;
+      case Launch::TRSM:
+        e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
+        break;
+      case Launch::MAXABS:
+        e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
+        break;
+      case Launch::CAST:
+        e = launch_cast(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec, sm,
+                        c->ws, c->dst, s);
+        break;
+      case Launch::GEMM:
+        e = launch_gemm(Lc.prec, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count, Lc.total,
+                        c->part, sm, c->dst, s);
+        break;
+    }
+    prof_end(c, pk, s);
+    if (e != hipSuccess) return MPCHOL_HIP_ERROR;
+  }
+  return 0;
+}
+
+static int status_from(const DevStatus& h, mpchol_info* info) {
+  int st = MPCHOL_OK;
+  int64_t fi = 0;
+  if (h.failed != ~0ull) {
+    st = MPCHOL_NOT_SPD;
+    fi = (int64_t)h.failed;
+  } else if (h.nonfinite) {
+    st = MPCHOL_NONFINITE;
+  } else if (h.wait_timeout) {
+    st = MPCHOL_HIP_ERROR;
+  }
+  if (info) {
+    info->status = st;
+    info->failed_index = fi;
+  }
+  return st;
+}
+
+extern "C" {
+
+const char* mpchol_version(void) { return "mpchol 0.1 (gfx950, HIP)"; }
+
+int mpchol_create(mpchol_ctx* ctx, int device) {
+  if (!ctx) return -1;
+  *ctx = nullptr;
+  std::unique_ptr<mpchol_ctx_s> c(new mpchol_ctx_s());
+  c->device = device;
+  HIPCHK(hipSetDevice(device));
+  HIPCHK(hipMalloc((void**)&c->dst, sizeof(DevStatus)));
+  HIPCHK(hipHostMalloc((void**)&c->hst, sizeof(DevStatus), hipHostMallocDefault));
+  HIPCHK(hipMalloc((void**)&c->npart, sizeof(double) * kNormParts * kMaxRhs * 2));
+  HIPCHK(hipHostMalloc((void**)&c->hnpart, sizeof(double) * kNormParts * kMaxRhs * 2,
+                       hipHostMallocDefault));
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+  *ctx = c.release();
+  return 0;
+}
+
+int mpchol_destroy(mpchol_ctx c) {
+  if (!c) return 0;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->plans) free_plan(*kv.second);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->part) (void)hipFree(c->part);
+  if (c->rbuf) (void)hipFree(c->rbuf);
+  if (c->npart) (void)hipFree(c->npart);
+  if (c->hnpart) (void)hipHostFree(c->hnpart);
+  if (c->dst) (void)hipFree(c->dst);
+  if (c->hst) (void)hipHostFree(c->hst);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  delete c;
+  return 0;
+}
+
+int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double* L, int64_t ldl,
+                  const mpchol_tree* tree, void* stream, mpchol_info* info) {
+  if (!c) return -1;
+  if (n < 0) return -2;
+  if (!A && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (!L && n > 0) return -5;
+  if (ldl < std::max<int64_t>(1, n)) return -6;
+  int v = validate_tree(tree);
+  if (v) return v;
+  if (L == A && ldl != lda) return -6;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  Plan* P = nullptr;
+  int r = get_plan(c, n, ldl, tree, &P);
+  if (r) return r;
+  r = ensure_ws(c, std::max<size_t>(P->ws_bytes, 256), std::max<int64_t>(P->parts, 1));
+  if (r) return r;
+  if (info) HIPCHK(hipEventRecord(c->ev0, s));
+  HIPCHK(launch_status_init(c->dst, s));
+  if (L != A) HIPCHK(launch_copy_lower(A, lda, L, ldl, n, s));
+  r = run_plan(c, *P, L, ldl, s);
+  if (r) return r;
+  HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  if (!info) return 0;
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  info->ms_factor = ms;
+  return status_from(*c->hst, info);
+}
+
+// X <- L^-T L^-1 X for up to kMaxRhs columns at a time.
+static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
+                              int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
+  for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+    int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
+    HIPCHK(launch_ticket_reset(c->dst, s));
+    HIPCHK(launch_trsv(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 0, s));
+    HIPCHK(launch_trsv(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 2, s));
+  }
+  return 0;
+}
+
+int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                 const double* L, int64_t ldl, const double* B, int64_t ldb, double* X,
+                 int64_t ldx, double tol, int32_t max_iter, void* stream, mpchol_info* info) {
+  if (!c) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (A && lda < std::max<int64_t>(1, n)) return -5;
+  if (!L && n > 0) return -6;
+  if (ldl < std::max<int64_t>(1, n)) return -7;
+  if (!B && n > 0 && nrhs > 0) return -8;
+  if (ldb < std::max<int64_t>(1, n)) return -9;
+  if (!X && n > 0 && nrhs > 0) return -10;
+  if (ldx < std::max<int64_t>(1, n)) return -11;
+  if (max_iter < 0) return -13;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipEventRecord(c->ev0, s));
+  HIPCHK(launch_status_init(c->dst, s));
+  HIPCHK(launch_copy_cols(n, (int)nrhs, B, ldb, X, ldx, s));
+  int r = chol_solve_inplace(c, n, nrhs, L, ldl, X, ldx, s);
+  if (r) return r;
+  int status = MPCHOL_OK;
+  int iters = 0;
+  double corr = 0.0;
+  if (A && max_iter > 0) {
+    if (c->rbuf_count < n * nrhs) {
+      HIPCHK(hipStreamSynchronize(s));
+      if (c->rbuf) HIPCHK(hipFree(c->rbuf));
+      c->rbuf = nullptr;
+      HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
+      c->rbuf_count = n * nrhs;
+    }
+    double* R = c->rbuf;
+    double prev = INFINITY;
+    int grew = 0;
+    status = MPCHOL_NOT_CONVERGED;
+    for (int it = 1; it <= max_iter; it++) {
+      for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+        int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
+        HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
+                               s));
+      }
+      r = chol_solve_inplace(c, n, nrhs, L, ldl, R, n, s);
+      if (r) return r;
+      double worst = 0.0;
+      bool bad = false;
+      for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+        int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
+        HIPCHK(launch_update_norms(n, nc, X + c0 * ldx, ldx, R + c0 * n, n, c->npart, kNormParts,
+                                   nullptr, s));
+        HIPCHK(hipMemcpyAsync(c->hnpart, c->npart, sizeof(double) * kNormParts * nc * 2,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int cc = 0; cc < nc; cc++) {
+          double dm = 0.0, xm = 0.0;
+          for (int w = 0; w < kNormParts; w++) {
+            dm = std::max(dm, c->hnpart[(w * nc + cc) * 2 + 0]);
+            xm = std::max(xm, c->hnpart[(w * nc + cc) * 2 + 1]);
+          }
+          if (!std::isfinite(dm) || !std::isfinite(xm)) bad = true;
+          double rr = xm > 0.0 ? dm / xm : dm;
+          worst = std::max(worst, rr);
+        }
+      }
+      iters = it;
+      corr = worst;
+      if (bad) {
+        status = MPCHOL_NONFINITE;
+        break;
+      }
+      if (worst <= tol) {
+        status = MPCHOL_OK;
+        break;
+      }
+      if (worst > prev) {
+        if (++grew >= 2) break;
+      } else {
+        grew = 0;
+      }
+      prev = worst;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (c->hst->wait_timeout) status = MPCHOL_HIP_ERROR;
+  if (info) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    info->ms_solve = ms;
+    info->status = status;
+    info->ir_iters = iters;
+    info->final_rel_corr = corr;
+  }
+  return status;
+}
+
+int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
+                          const double* const* A_dev, const int64_t* lda_host,
+                          double* const* L_dev, const int64_t* ldl_host, int64_t nrhs,
+                          const double* const* B_dev, double* const* X_dev, double tol,
+                          int32_t max_iter, const mpchol_tree* tree, void* stream,
+                          mpchol_info* info_host) {
+  if (!c) return -1;
+  if (batch < 0) return -2;
+  if (batch > 0 && (!n_host || !A_dev || !lda_host || !L_dev || !ldl_host)) return -3;
+  int v = validate_tree(tree);
+  if (v) return v;
+  int worst = 0;
+  for (int64_t i = 0; i < batch; i++) {
+    mpchol_info fi{}, si{};
+    int r = mpchol_factor(c, n_host[i], A_dev[i], lda_host[i], L_dev[i], ldl_host[i], tree,
+                          stream, &fi);
+    if (r < 0) return r;
+    if (r == 0 && nrhs > 0 && B_dev && X_dev) {
+      r = mpchol_solve(c, n_host[i], nrhs, A_dev[i], lda_host[i], L_dev[i], ldl_host[i], B_dev[i],
+                       n_host[i], X_dev[i], n_host[i], tol, max_iter, stream, &si);
+      if (r < 0) return r;
+    }
+    if (info_host) {
+      info_host[i] = fi;
+      info_host[i].ir_iters = si.ir_iters;
+      info_host[i].final_rel_corr = si.final_rel_corr;
+      info_host[i].ms_solve = si.ms_solve;
+      if (fi.status == 0) info_host[i].status = si.status;
+    }
+    worst = std::max(worst, r);
+  }
+  return worst;
+}
+
+// Quantize one column-major block with its power-of-two block scale into a
+// K-contiguous copy (the operation every low-precision GEMM operand goes
+// through).  Synchronizes the stream.
+int mpchol_quantize(mpchol_ctx c, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                    int32_t prec, int32_t scale_mode, void* dst, int64_t ldq, double* scale_out,
+                    void* stream) {
+  if (!c) return -1;
+  if (rows < 0) return -2;
+  if (cols < 0) return -3;
+  if (!src && rows > 0 && cols > 0) return -4;
+  if (lds < std::max<int64_t>(1, rows)) return -5;
+  if (prec != MPCHOL_F16 && prec != MPCHOL_E4M3) return -6;
+  if (scale_mode < 0 || scale_mode > 1) return -7;
+  if (!dst && rows > 0) return -8;
+  if (ldq < ((cols + 15) / 16) * 16) return -9;
+  if (rows > INT32_MAX || cols > INT32_MAX || ldq > INT32_MAX) return -2;
+  if (rows == 0 || cols == 0) {
+    if (scale_out) *scale_out = 1.0;
+    return 0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  MaxabsJob mj{};
+  mj.src = 0;
+  mj.rows = (int)rows;
+  mj.cols = (int)cols;
+  int np = (int)std::min<int64_t>(128, cols);
+  mj.cpw = (int)((cols + np - 1) / np);
+  mj.nparts = (int)((cols + mj.cpw - 1) / mj.cpw);
+  mj.part0 = 0;
+  mj.wg_start = 0;
+  CastJob cj{};
+  cj.src = 0;
+  cj.dst = 0;
+  cj.rows = (int)rows;
+  cj.cols = (int)cols;
+  cj.ldq = (int)ldq;
+  cj.part0 = 0;
+  cj.nparts = mj.nparts;
+  cj.tiles_r = (int)((rows + 63) / 64);
+  cj.tiles_c = (int)((ldq + 63) / 64);
+  cj.wg_start = 0;
+  int r = ensure_ws(c, 256, mj.nparts);
+  if (r) return r;
+  MaxabsJob* dm = nullptr;
+  CastJob* dc = nullptr;
+  HIPCHK(hipMalloc((void**)&dm, sizeof(mj)));
+  HIPCHK(hipMalloc((void**)&dc, sizeof(cj)));
+  HIPCHK(hipMemcpyAsync(dm, &mj, sizeof(mj), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dc, &cj, sizeof(cj), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_status_init(c->dst, s));
+  HIPCHK(launch_maxabs(src, lds, dm, 1, mj.nparts, c->part, s));
+  HIPCHK(launch_cast(src, lds, dc, 1, cj.tiles_r * cj.tiles_c, c->part, prec, scale_mode, dst,
+                     c->dst, s));
+  std::vector<double> hp(mj.nparts);
+  HIPCHK(hipMemcpyAsync(hp.data(), c->part, sizeof(double) * mj.nparts, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFree(dm));
+  HIPCHK(hipFree(dc));
+  double mx = 0.0;
+  for (double v : hp) mx = std::max(mx, v);
+  bool bad = !(mx <= 1.7976931348623157e308);
+  if (scale_out) *scale_out = bad ? 1.0 : block_scale(mx, prec, scale_mode);
+  return c->hst->nonfinite ? MPCHOL_NONFINITE : 0;
+}
+
+int mpchol_profile(mpchol_ctx c, uint32_t kind_mask) {
+  if (!c) return -1;
+  if (prof_collect(c)) return MPCHOL_HIP_ERROR;
+  c->prof_mask = kind_mask;
+  for (int k = 0; k < MPCHOL_PROF_KINDS; k++) {
+    c->acc_ms[k] = 0.0;
+    c->acc_work[k] = 0.0;
+    c->acc_n[k] = 0;
+  }
+  return 0;
+}
+
+int mpchol_profile_read(mpchol_ctx c, double* ms, double* work, int64_t* launches) {
+  if (!c) return -1;
+  if (prof_collect(c)) return MPCHOL_HIP_ERROR;
+  for (int k = 0; k < MPCHOL_PROF_KINDS; k++) {
+    if (ms) ms[k] = c->acc_ms[k];
+    if (work) work[k] = c->acc_work[k];
+    if (launches) launches[k] = c->acc_n[k];
+  }
+  return 0;
+}
+
+// Plan introspection (host only, no device needed): flops by precision,
+// leaf flops, quantize-cast bytes, launch count and workspace of (n, ldl, tree).
+int mpchol_plan_stats(int64_t n, int64_t ldl, const mpchol_tree* tree, double* flops4,
+                      double* leaf_flops, double* cast_bytes, int64_t* launches,
+                      int64_t* ws_bytes) {
+  if (n < 0) return -1;
+  if (ldl < std::max<int64_t>(1, n)) return -2;
+  int v = validate_tree(tree);
+  if (v) return v;
+  Plan P;
+  build_plan(P, n, ldl, tree);
+  for (int i = 0; i < 4; i++) flops4[i] = P.stats.flops[i];
+  *leaf_flops = P.stats.leaf_flops;
+  *cast_bytes = P.stats.cast_bytes;
+  *launches = P.stats.n_launch;
+  *ws_bytes = (int64_t)P.ws_bytes;
+  return 0;
+}
+
+}  // extern "C"

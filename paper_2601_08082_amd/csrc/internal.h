@@ -1,0 +1,96 @@
+// Internal declarations shared by the host planner/executor and the HIP
+// kernels of libmpchol.  Not part of the public C-ABI (include/mpchol.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpc {
+
+enum Prec : int32_t { E4M3 = 0, F16 = 1, F32 = 2, F64 = 3 };
+
+// Largest leaf handled by a single leaf-POTRF / leaf-TRSM kernel.  Larger
+// leaves of the precision tree are factored by an all-leaf-precision
+// sub-recursion down to this size (any FP64 Cholesky of the leaf is a valid
+// leaf POTRF).
+constexpr int kKernelLeaf = 64;
+
+// Device status words of a context.
+struct DevStatus {
+  unsigned long long failed;   // min over bad pivots of (1-based column); ~0 = none
+  unsigned int nonfinite;      // a quantized block or a solve produced Inf/NaN
+  unsigned int wait_timeout;   // a bounded spin-wait gave up (kernel exited early)
+  unsigned int ticket[4];      // dynamic work tickets (triangular solves)
+};
+
+// Max-abs over an operand block: WG w of the job reduces columns
+// [w*cpw, min(cols,(w+1)*cpw)) of the block into part[part0 + w].
+struct MaxabsJob {
+  int64_t src;       // element offset of the block in the factor matrix
+  int32_t rows, cols;
+  int32_t part0;     // first partial slot
+  int32_t nparts;    // number of workgroups (= partial slots) for this job
+  int32_t cpw;       // columns per workgroup
+  int32_t wg_start;  // prefix sum of workgroups over the job list
+};
+
+// Quantize an operand block into a K-contiguous workspace copy:
+// dst[r * ldq + c] = RNE_p(src(r, c) / s), zero for cols <= c < ldq.
+struct CastJob {
+  int64_t src;       // element offset in the factor matrix
+  int64_t dst;       // element offset in the workspace (units of the format)
+  int32_t rows, cols;
+  int32_t ldq;       // row stride of the copy (multiple of 8, >= cols)
+  int32_t part0, nparts;  // partial maxabs of this block
+  int32_t tiles_r;   // 64-row tiles
+  int32_t tiles_c;   // 64-col tiles over ldq
+  int32_t wg_start;
+};
+
+// One GEMM problem of a grouped launch:  C(m x n) -= sx*sy * X(m x k) Y(n x k)^T
+// with C a block of the factor (column-major, ld = ldc of the launch).
+// F16/E4M3: X, Y are K-contiguous workspace copies (ldx, ldy); F32/F64: X, Y are
+// blocks of the factor (column-major, ld = ldc).  lower: C is a diagonal block
+// and only C(i, j), i >= j, is written.
+struct GemmProb {
+  int64_t c, x, y;
+  int32_t m, n, k;
+  int32_t ldx, ldy;
+  int32_t xpart0, xnparts, ypart0, ynparts;  // maxabs partials (nparts = 0: scale 1)
+  int32_t lower;
+  int32_t tiles_m, tiles_n;
+  int32_t tile_start;  // prefix sum of tiles over the problem list
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+hipError_t launch_status_init(DevStatus* st, hipStream_t s);
+hipError_t launch_copy_lower(const double* A, int64_t lda, double* L, int64_t ldl, int64_t n,
+                             hipStream_t s);
+hipError_t launch_maxabs(const double* Lm, int64_t ldl, const MaxabsJob* jobs, int njobs,
+                         int total_wg, double* part, hipStream_t s);
+hipError_t launch_cast(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
+                       int total_wg, const double* part, int prec, int scale_mode, void* ws,
+                       DevStatus* st, hipStream_t s);
+hipError_t launch_gemm(int prec, double* Lm, int64_t ldl, const void* ws, const GemmProb* probs,
+                       int nprobs, int total_tiles, const double* part, int scale_mode,
+                       DevStatus* st, hipStream_t s);
+hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m,
+                             DevStatus* st, hipStream_t s);
+hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,
+                            int64_t c0, int k, hipStream_t s);
+
+// Solve / refinement kernels.
+hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs,
+                       double* X, int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s);
+hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
+                           int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
+                           hipStream_t s);
+hipError_t launch_update_norms(int64_t n, int nrhs, double* X, int64_t ldx, const double* D,
+                               int64_t ldd, double* part, int nparts, double* out,
+                               hipStream_t s);
+hipError_t launch_copy_cols(int64_t n, int nrhs, const double* src, int64_t lds, double* dst,
+                            int64_t ldd, hipStream_t s);
+hipError_t launch_ticket_reset(DevStatus* st, hipStream_t s);
+
+}  // namespace mpc

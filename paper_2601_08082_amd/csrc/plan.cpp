@@ -1,0 +1,346 @@
+// Planner: walks Tree-POTRF (Algorithm 1), Tree-TRSM (Algorithm 2) and
+// Tree-SYRK (Algorithm 3) on the host once per (n, ldl, descriptor) and emits
+// the launches that carry them out on the GPU, in an order that respects every
+// data dependency of the recursion (one stream):
+//
+//  - a GEMM issued by a Tree-POTRF node at depth l runs in that node's
+//    precision (offdiag[min(l, nlevels-1)] or node_prec[node]); FP16 / E4M3
+//    operands are quantized first (max-abs, power-of-two scale, cast), FP32
+//    operands are scaled and rounded while loaded, FP64 operands are used as is;
+//  - every GEMM and leaf SYRK of one Tree-SYRK is independent of the others
+//    (disjoint outputs, read-only operand panel), so each Tree-SYRK becomes one
+//    max-abs launch, one cast launch and one grouped GEMM launch per precision;
+//  - Tree-TRSM is a chain (each GEMM consumes the previous leaf solve);
+//  - a leaf of the precision tree larger than the kernel leaf (64) is factored
+//    / solved by an all-leaf-precision sub-recursion down to 64; this is a
+//    leaf-precision Cholesky (resp. triangular solve) of that leaf.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <sstream>
+
+namespace mpc {
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+int64_t split_rule(int64_t m, int32_t align) {
+  int64_t h = m / 2;
+  if (align > 1) h = cdiv(h, align) * align;
+  if (h < 1) h = 1;
+  if (h > m - 1) h = m - 1;
+  return h;
+}
+
+int validate_tree(const mpchol_tree* t) {
+  if (!t) return -7;
+  if (t->abi_version != MPCHOL_ABI_VERSION) return -7;
+  if (t->leaf < 1 || t->split_align < 1) return -7;
+  if (t->nlevels < 1 || t->nlevels > MPCHOL_MAX_LEVELS) return -7;
+  for (int i = 0; i < t->nlevels; i++)
+    if (t->offdiag[i] < MPCHOL_E4M3 || t->offdiag[i] > MPCHOL_F64) return -7;
+  if (t->leaf_prec != MPCHOL_F32 && t->leaf_prec != MPCHOL_F64) return -7;
+  if (t->syrk_leaf_mode < 0 || t->syrk_leaf_mode > 1) return -7;
+  if (t->scale_mode < 0 || t->scale_mode > 1) return -7;
+  if (t->scale_tile != 0) return MPCHOL_NOT_SUPPORTED;
+  if (t->n_nodes < 0 || (t->n_nodes > 0 && !t->node_prec)) return -7;
+  for (int64_t i = 0; i < t->n_nodes; i++)
+    if (t->node_prec[i] > MPCHOL_F64) return -7;
+  return 0;
+}
+
+std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t) {
+  std::ostringstream o;
+  o << n << ':' << ldl << ':' << t->leaf << ':' << t->split_align << ':' << t->leaf_prec << ':'
+    << t->syrk_leaf_mode << ':' << t->scale_mode << ':';
+  for (int i = 0; i < t->nlevels; i++) o << t->offdiag[i] << ',';
+  o << ':';
+  for (int64_t i = 0; i < t->n_nodes; i++) o << (int)t->node_prec[i] << ',';
+  return o.str();
+}
+
+namespace {
+
+constexpr int kMaxParts = 128;
+
+struct Builder {
+  Plan& P;
+  const mpchol_tree& t;
+  int64_t ldl;
+  int64_t next_node = 0;
+  size_t ws_cursor = 0;   // bytes used by the current group of quantized copies
+  int64_t part_cursor = 0;
+
+  Builder(Plan& p, const mpchol_tree& tr, int64_t ld) : P(p), t(tr), ldl(ld) {}
+
+  int64_t off(int64_t r, int64_t c) const { return r + c * ldl; }
+
+  int node_prec(int64_t id, int depth) const {
+    if (id < (int64_t)P.node_prec.size() && P.node_prec[id] >= 0) return P.node_prec[id];
+    return t.offdiag[std::min(depth, t.nlevels - 1)];
+  }
+
+  void begin_group() {
+    ws_cursor = 0;
+    part_cursor = 0;
+  }
+  void end_group() {
+    P.ws_bytes = std::max(P.ws_bytes, ws_cursor);
+    P.parts = std::max(P.parts, part_cursor);
+  }
+
+  // Max-abs job for block (r, c, rows, cols); returns (part0, nparts).
+  std::pair<int, int> add_maxabs(std::vector<MaxabsJob>& jobs, int64_t r, int64_t c, int rows,
+                                 int cols) {
+    MaxabsJob j{};
+    j.src = off(r, c);
+    j.rows = rows;
+    j.cols = cols;
+    int np = std::min(kMaxParts, cols);
+    j.cpw = (int)cdiv(cols, np);
+    j.nparts = (int)cdiv(cols, j.cpw);
+    j.part0 = (int)part_cursor;
+    part_cursor += j.nparts;
+    jobs.push_back(j);
+    return {j.part0, j.nparts};
+  }
+
+  int64_t add_cast(std::vector<CastJob>& jobs, int prec, int64_t r, int64_t c, int rows, int cols,
+                   std::pair<int, int> parts, int* ldq_out) {
+    int esz = prec == F16 ? 2 : 1;
+    CastJob j{};
+    j.src = off(r, c);
+    j.rows = rows;
+    j.cols = cols;
+    j.ldq = (int)rup(cols, 16);
+    ws_cursor = (size_t)rup((int64_t)ws_cursor, 256);
+    j.dst = (int64_t)(ws_cursor / esz);
+    ws_cursor += (size_t)rows * j.ldq * esz;
+    j.part0 = parts.first;
+    j.nparts = parts.second;
+    j.tiles_r = (int)cdiv(rows, 64);
+    j.tiles_c = (int)cdiv(j.ldq, 64);
+    jobs.push_back(j);
+    P.stats.cast_bytes += (double)rows * cols * (8.0 + esz);
+    *ldq_out = j.ldq;
+    return j.dst;
+  }
+
+  struct Node {
+    int64_t cr, cc;  // C block origin
+    int m, n;        // C block size
+    int64_t xr, xc;  // X block origin (m x k)
+    int64_t yr, yc;  // Y block origin (n x k)
+    int k;
+    int lower;
+    int prec;
+  };
+
+  // Emit maxabs / cast / grouped GEMM launches for independent GEMM nodes that
+  // share one precision.
+  void emit_group(const std::vector<Node>& nodes, int prec, bool with_parts) {
+    if (nodes.empty()) return;
+    begin_group();
+    std::vector<MaxabsJob> mj;
+    std::vector<CastJob> cj;
+    std::vector<GemmProb> gp;
+    const bool quant = prec == F16 || prec == E4M3;
+    for (const Node& nd : nodes) {
+      GemmProb g{};
+      g.c = off(nd.cr, nd.cc);
+      g.m = nd.m;
+      g.n = nd.n;
+      g.k = nd.k;
+      g.lower = nd.lower;
+      g.tiles_m = (int)cdiv(nd.m, 128);
+      g.tiles_n = (int)cdiv(nd.n, 128);
+      std::pair<int, int> px{0, 0}, py{0, 0};
+      if (with_parts) {
+        px = add_maxabs(mj, nd.xr, nd.xc, nd.m, nd.k);
+        py = nd.lower ? px : add_maxabs(mj, nd.yr, nd.yc, nd.n, nd.k);
+      }
+      g.xpart0 = px.first;
+      g.xnparts = px.second;
+      g.ypart0 = py.first;
+      g.ynparts = py.second;
+      if (quant) {
+        int ldx = 0, ldy = 0;
+        g.x = add_cast(cj, prec, nd.xr, nd.xc, nd.m, nd.k, px, &ldx);
+        g.ldx = ldx;
+        if (nd.lower) {
+          g.y = g.x;
+          g.ldy = ldx;
+        } else {
+          g.y = add_cast(cj, prec, nd.yr, nd.yc, nd.n, nd.k, py, &ldy);
+          g.ldy = ldy;
+        }
+      } else {
+        g.x = off(nd.xr, nd.xc);
+        g.y = off(nd.yr, nd.yc);
+        g.ldx = g.ldy = (int)ldl;
+      }
+      double fl = nd.lower ? (double)nd.m * (nd.m + 1) * nd.k : 2.0 * nd.m * nd.n * nd.k;
+      P.stats.flops[prec] += fl;
+      gp.push_back(g);
+    }
+    if (!mj.empty()) {
+      Launch L{Launch::MAXABS, prec};
+      L.first = (int)P.maxabs.size();
+      L.count = (int)mj.size();
+      int wg = 0;
+      for (auto& j : mj) {
+        j.wg_start = wg;
+        wg += j.nparts;
+      }
+      L.total = wg;
+      P.maxabs.insert(P.maxabs.end(), mj.begin(), mj.end());
+      P.launches.push_back(L);
+    }
+    if (!cj.empty()) {
+      Launch L{Launch::CAST, prec};
+      L.first = (int)P.casts.size();
+      L.count = (int)cj.size();
+      int wg = 0;
+      for (auto& j : cj) {
+        j.wg_start = wg;
+        wg += j.tiles_r * j.tiles_c;
+      }
+      L.total = wg;
+      P.casts.insert(P.casts.end(), cj.begin(), cj.end());
+      P.launches.push_back(L);
+    }
+    {
+      Launch L{Launch::GEMM, prec};
+      L.first = (int)P.gemms.size();
+      L.count = (int)gp.size();
+      int tiles = 0;
+      for (auto& g : gp) {
+        g.tile_start = tiles;
+        tiles += g.lower ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
+      }
+      L.total = tiles;
+      P.gemms.insert(P.gemms.end(), gp.begin(), gp.end());
+      P.launches.push_back(L);
+    }
+    end_group();
+  }
+
+  void gemm_one(const Node& nd, bool with_parts) { emit_group({nd}, nd.prec, with_parts); }
+
+  // ---- leaf precision: kernels of size <= kKernelLeaf, sub-recursion above
+  int64_t leaf_split(int64_t m) const {
+    int64_t h = cdiv(m / 2, kKernelLeaf) * kKernelLeaf;
+    return std::max<int64_t>(1, std::min(h, m - 1));
+  }
+
+  void leaf_potrf(int64_t i0, int64_t m) {
+    if (m <= 0) return;
+    if (m <= kKernelLeaf) {
+      Launch L{Launch::POTRF, t.leaf_prec};
+      L.a0 = i0;
+      L.a1 = m;
+      P.launches.push_back(L);
+      P.stats.leaf_flops += (double)m * m * m / 3.0;
+      return;
+    }
+    int64_t m1 = leaf_split(m), m2 = m - m1;
+    leaf_potrf(i0, m1);
+    leaf_trsm(i0 + m1, m2, i0, m1);
+    gemm_one(Node{i0 + m1, i0 + m1, (int)m2, (int)m2, i0 + m1, i0, i0 + m1, i0, (int)m1, 1,
+                  t.leaf_prec},
+             false);
+    leaf_potrf(i0 + m1, m2);
+  }
+
+  void leaf_trsm(int64_t r0, int64_t m, int64_t c0, int64_t k) {
+    if (m <= 0 || k <= 0) return;
+    if (k <= kKernelLeaf) {
+      Launch L{Launch::TRSM, t.leaf_prec};
+      L.a0 = r0;
+      L.a1 = m;
+      L.a2 = c0;
+      L.a3 = k;
+      P.launches.push_back(L);
+      P.stats.leaf_flops += (double)m * k * k;
+      return;
+    }
+    int64_t k1 = leaf_split(k), k2 = k - k1;
+    leaf_trsm(r0, m, c0, k1);
+    gemm_one(Node{r0, c0 + k1, (int)m, (int)k2, r0, c0, c0 + k1, c0, (int)k1, 0, t.leaf_prec},
+             false);
+    leaf_trsm(r0, m, c0 + k1, k2);
+  }
+
+  // ---- Algorithm 2: B <- B L^{-T}, B = (r0, c0, m x k), L = (c0, c0, k x k)
+  void trsm(int64_t r0, int64_t m, int64_t c0, int64_t k, int prec) {
+    if (m <= 0 || k <= 0) return;
+    if (std::min(m, k) <= t.leaf) {
+      leaf_trsm(r0, m, c0, k);
+      return;
+    }
+    int64_t k1 = split_rule(k, t.split_align), k2 = k - k1;
+    trsm(r0, m, c0, k1, prec);
+    gemm_one(Node{r0, c0 + k1, (int)m, (int)k2, r0, c0, c0 + k1, c0, (int)k1, 0, prec},
+             prec != F64);
+    trsm(r0, m, c0 + k1, k2, prec);
+  }
+
+  // ---- Algorithm 3: C <- C - P P^T (lower), C = (c0, c0, s x s), P = (c0, p0, s x K)
+  void syrk_collect(int64_t c0, int64_t s, int64_t p0, int64_t K, int prec,
+                    std::vector<Node>& out) {
+    if (s <= 0) return;
+    if (s <= t.leaf) {
+      int p = t.syrk_leaf_mode ? t.leaf_prec : prec;
+      out.push_back(Node{c0, c0, (int)s, (int)s, c0, p0, c0, p0, (int)K, 1, p});
+      return;
+    }
+    int64_t s1 = split_rule(s, t.split_align), s2 = s - s1;
+    syrk_collect(c0, s1, p0, K, prec, out);
+    out.push_back(Node{c0 + s1, c0, (int)s2, (int)s1, c0 + s1, p0, c0, p0, (int)K, 0, prec});
+    syrk_collect(c0 + s1, s2, p0, K, prec, out);
+  }
+
+  void syrk(int64_t c0, int64_t s, int64_t p0, int64_t K, int prec) {
+    if (s <= 0 || K <= 0) return;
+    std::vector<Node> all;
+    syrk_collect(c0, s, p0, K, prec, all);
+    for (int q = E4M3; q <= F64; q++) {
+      std::vector<Node> sel;
+      for (auto& nd : all)
+        if (nd.prec == q) sel.push_back(nd);
+      emit_group(sel, q, q != F64);
+    }
+  }
+
+  // ---- Algorithm 1
+  void potrf(int64_t i0, int64_t m, int depth) {
+    if (m <= 0) return;
+    if (m <= t.leaf) {
+      leaf_potrf(i0, m);
+      return;
+    }
+    int64_t id = next_node++;
+    int p = node_prec(id, depth);
+    int64_t m1 = split_rule(m, t.split_align), m2 = m - m1;
+    potrf(i0, m1, depth + 1);
+    trsm(i0 + m1, m2, i0, m1, p);
+    syrk(i0 + m1, m2, i0, m1, p);
+    potrf(i0 + m1, m2, depth + 1);
+  }
+};
+
+}  // namespace
+
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t) {
+  P.n = n;
+  P.ldl = ldl;
+  P.tree = *t;
+  P.node_prec.assign(t->node_prec, t->node_prec + t->n_nodes);
+  P.tree.node_prec = nullptr;
+  Builder B(P, P.tree, ldl);
+  B.potrf(0, n, 0);
+  P.stats.n_launch = (int64_t)P.launches.size();
+}
+
+}  // namespace mpc

@@ -1,0 +1,51 @@
+// Host-side plan of one factorization: the recursion of Algorithms 1-3 unrolled
+// into an ordered list of kernel launches with their descriptor arrays.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mpchol.h"
+#include "internal.h"
+
+namespace mpc {
+
+struct Launch {
+  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM } kind;
+  int prec;
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF: i0, m; TRSM: r0, m, c0, k
+  int first = 0, count = 0, total = 0;    // descriptor range, workgroups
+};
+
+struct PlanStats {
+  double flops[4] = {0, 0, 0, 0};  // GEMM/SYRK flops by precision (E4M3, F16, F32, F64)
+  double leaf_flops = 0;           // leaf POTRF + leaf TRSM
+  double cast_bytes = 0;           // algorithmic bytes of quantize casts
+  int64_t n_launch = 0;
+};
+
+struct Plan {
+  int64_t n = 0, ldl = 0;
+  mpchol_tree tree{};
+  std::vector<int8_t> node_prec;
+  std::vector<Launch> launches;
+  std::vector<MaxabsJob> maxabs;
+  std::vector<CastJob> casts;
+  std::vector<GemmProb> gemms;
+  size_t ws_bytes = 0;     // quantized-operand workspace needed
+  int64_t parts = 0;       // maxabs partial slots needed
+  PlanStats stats;
+  // device copies of the descriptor arrays
+  MaxabsJob* d_maxabs = nullptr;
+  CastJob* d_casts = nullptr;
+  GemmProb* d_gemms = nullptr;
+};
+
+// Validates the descriptor; returns 0 or a negative/positive mpchol code.
+int validate_tree(const mpchol_tree* t);
+std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t);
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t);
+int64_t split_rule(int64_t m, int32_t align);
+
+}  // namespace mpc
