@@ -208,7 +208,8 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
 // FP32 / FP64 operands read straight from the factor (column-major).  FP32
 // operands are rounded (RNE) from FP64 after scaling on the way into LDS.
 // v_mfma_{f32_16x16x4f32, f64_16x16x4f64}: lane l holds A(l%16, k = l/16);
-// D(i, j) for lane l, register r: j = l%16, i = 4*(l/16) + r.
+// D(i, j) for lane l, register r: j = l%16 and i = 4*(l/16) + r (FP32) or
+// i = l/16 + 4*r (FP64), as measured on gfx950.
 
 template <typename T> struct DOps;
 template <> struct DOps<float> {
@@ -317,7 +318,8 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
       const int m = m0 + wm * 64 + b * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int n = n0 + wn * 64 + a * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 64 + a * 16 +
+                      (sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         if (m < P.m && n < P.n && (!P.lower || m >= n)) {
           double* p = C + m + (int64_t)n * ldl;
           *p = *p - sxy * (double)acc[a][b][r];

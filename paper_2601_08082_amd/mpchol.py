@@ -66,6 +66,9 @@ def _load() -> ct.CDLL:
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with paper_2601_08082_amd/build.py "
             "(hipcc, gfx950); there is no CPU fallback")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that this library binds to the runtime that owns torch's allocations
+    import torch  # noqa: F401
     lib = ct.CDLL(LIB_PATH)
     vp, i64, i32, dbl = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_double
     lib.mpchol_create.argtypes = [ct.POINTER(vp), ct.c_int]

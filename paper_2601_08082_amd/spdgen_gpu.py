@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(_HERE, "libspdgen.so")
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build with paper_2601_08082_amd/build.py")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that this library binds to the runtime that owns torch's allocations
+    import torch  # noqa: F401
     lib = ct.CDLL(LIB_PATH)
     lib.spdgen_fill.argtypes = [ct.c_int64, ct.c_int64, ct.c_double, ct.c_double, ct.c_uint64,
                                 ct.c_void_p, ct.c_void_p]
