@@ -201,8 +201,8 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
                         c->ws, c->dst, s);
         break;
       case Launch::GEMM:
-        e = launch_gemm(Lc.prec, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count, Lc.total,
-                        c->part, sm, c->dst, s);
+        e = launch_gemm(Lc.prec, Lc.tile, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count,
+                        Lc.total, c->part, sm, c->dst, s);
         break;
     }
     prof_end(c, pk, s);

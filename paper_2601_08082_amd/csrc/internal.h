@@ -12,7 +12,7 @@ enum Prec : int32_t { E4M3 = 0, F16 = 1, F32 = 2, F64 = 3 };
 // leaves of the precision tree are factored by an all-leaf-precision
 // sub-recursion down to this size (any FP64 Cholesky of the leaf is a valid
 // leaf POTRF).
-constexpr int kKernelLeaf = 64;
+constexpr int kKernelLeaf = 128;
 
 // Device status words of a context.
 struct DevStatus {
@@ -72,9 +72,9 @@ hipError_t launch_maxabs(const double* Lm, int64_t ldl, const MaxabsJob* jobs, i
 hipError_t launch_cast(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                        int total_wg, const double* part, int prec, int scale_mode, void* ws,
                        DevStatus* st, hipStream_t s);
-hipError_t launch_gemm(int prec, double* Lm, int64_t ldl, const void* ws, const GemmProb* probs,
-                       int nprobs, int total_tiles, const double* part, int scale_mode,
-                       DevStatus* st, hipStream_t s);
+hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* ws,
+                       const GemmProb* probs, int nprobs, int total_tiles, const double* part,
+                       int scale_mode, DevStatus* st, hipStream_t s);
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m,
                              DevStatus* st, hipStream_t s);
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,

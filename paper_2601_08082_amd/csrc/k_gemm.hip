@@ -98,14 +98,17 @@ template <> struct QOps<unsigned char> {
   }
 };
 
-template <typename Q>
+template <typename Q, int BM>
 __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t ldl,
                                                 const Q* __restrict__ ws,
                                                 const GemmProb* __restrict__ probs, int nprobs,
                                                 const double* __restrict__ part, int prec,
                                                 int scale_mode, DevStatus* st) {
   typedef typename QOps<Q>::vec vec;
-  constexpr int BM = 128, BN = 128;
+  constexpr int BN = BM;                         // square tiles: 128 or 64
+  constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
+  constexpr int NF = WT / 32;                    // 32 x 32 MFMA tiles per wave dimension
+  constexpr int NV = BM * 8 / 256;               // 16-byte vectors per thread per operand
   constexpr int EPV = 16 / (int)sizeof(Q);       // elements per 16-byte vector
   constexpr int BK = 128 / (int)sizeof(Q);       // elements per K step (128 bytes per row)
   constexpr int LDSW = BK + EPV;                 // padded LDS row (144 bytes)
@@ -127,10 +130,10 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  uint4 rx[4], ry[4];
+  uint4 rx[NV], ry[NV];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
       int row = v >> 3, ch = v & 7;
       int kk = k0 + ch * EPV;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
       int row = v >> 3, ch = v & 7;
       *reinterpret_cast<uint4*>(&Xs[buf][row * LDSW + ch * EPV]) = rx[i];
@@ -154,11 +157,11 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
     }
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[NF][NF];
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < NF; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+    for (int b = 0; b < NF; b++)
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[a][b][r] = 0.0f;
 
@@ -171,17 +174,17 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
 #pragma unroll
     for (int kk = 0; kk < BK / 16; kk++) {
       const int koff = kk * 16 + 8 * (lane >> 5);
-      vec af[2], bf[2];
+      vec af[NF], bf[NF];
 #pragma unroll
-      for (int a = 0; a < 2; a++)
-        af[a] = *reinterpret_cast<const vec*>(&Ys[cur][(wn * 64 + a * 32 + (lane & 31)) * LDSW + koff]);
+      for (int a = 0; a < NF; a++)
+        af[a] = *reinterpret_cast<const vec*>(&Ys[cur][(wn * WT + a * 32 + (lane & 31)) * LDSW + koff]);
 #pragma unroll
-      for (int b = 0; b < 2; b++)
-        bf[b] = *reinterpret_cast<const vec*>(&Xs[cur][(wm * 64 + b * 32 + (lane & 31)) * LDSW + koff]);
+      for (int b = 0; b < NF; b++)
+        bf[b] = *reinterpret_cast<const vec*>(&Xs[cur][(wm * WT + b * 32 + (lane & 31)) * LDSW + koff]);
 #pragma unroll
-      for (int a = 0; a < 2; a++)
+      for (int a = 0; a < NF; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++) acc[a][b] = QOps<Q>::mfma(af[a], bf[b], acc[a][b]);
+        for (int b = 0; b < NF; b++) acc[a][b] = QOps<Q>::mfma(af[a], bf[b], acc[a][b]);
     }
     if (kt + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
@@ -189,13 +192,13 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
 
   double* __restrict__ C = Lm + P.c;
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < NF; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) {
-      const int m = m0 + wm * 64 + b * 32 + (lane & 31);
+    for (int b = 0; b < NF; b++) {
+      const int m = m0 + wm * WT + b * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; r++) {
-        const int n = n0 + wn * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn * WT + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (m < P.m && n < P.n && (!P.lower || m >= n)) {
           double* p = C + m + (int64_t)n * ldl;
           *p = *p - sxy * (double)acc[a][b][r];
@@ -225,13 +228,17 @@ template <> struct DOps<double> {
   }
 };
 
-template <typename T>
+template <typename T, int BM>
 __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t ldl,
                                                 const GemmProb* __restrict__ probs, int nprobs,
                                                 const double* __restrict__ part, int prec,
                                                 int scale_mode, DevStatus* st) {
   typedef typename DOps<T>::acc_t acc_t;
-  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int BN = BM, BK = 16;                // square tiles: 128 or 64
+  constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
+  constexpr int NF = WT / 16;                    // 16 x 16 MFMA tiles per wave dimension
+  constexpr int NL = BM * BK / 256;              // elements per thread per operand and K step
+  constexpr int TPR = 256 / BM;                  // threads per k row in the loads
   constexpr int LDSW = sizeof(T) == 8 ? BM + 16 : BM + 32;  // row stride = 32 mod 64 dwords
   __shared__ T Xs[2][BK * LDSW];
   __shared__ T Ys[2][BK * LDSW];
@@ -251,12 +258,12 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  T rx[8], ry[8];
+  T rx[NL], ry[NL];
   auto gload = [&](int k0) {
-    const int mm = tid & 127;
+    const int mm = tid % BM;
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      int kk = k0 + (tid >> 7) + 2 * i;
+    for (int i = 0; i < NL; i++) {
+      int kk = k0 + (tid / BM) + TPR * i;
       bool kin = kk < P.k;
       double vx = (kin && m0 + mm < P.m) ? X[(m0 + mm) + (int64_t)kk * ldl] : 0.0;
       double vy = (kin && n0 + mm < P.n) ? Y[(n0 + mm) + (int64_t)kk * ldl] : 0.0;
@@ -270,20 +277,20 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
     }
   };
   auto sstore = [&](int buf) {
-    const int mm = tid & 127;
+    const int mm = tid % BM;
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      int kk = (tid >> 7) + 2 * i;
+    for (int i = 0; i < NL; i++) {
+      int kk = (tid / BM) + TPR * i;
       Xs[buf][kk * LDSW + mm] = rx[i];
       Ys[buf][kk * LDSW + mm] = ry[i];
     }
   };
 
-  acc_t acc[4][4];
+  acc_t acc[NF][NF];
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int a = 0; a < NF; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++)
+    for (int b = 0; b < NF; b++)
 #pragma unroll
       for (int r = 0; r < 4; r++) acc[a][b][r] = 0;
 
@@ -296,15 +303,15 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
 #pragma unroll
     for (int kk = 0; kk < BK / 4; kk++) {
       const int krow = kk * 4 + (lane >> 4);
-      T af[4], bf[4];
+      T af[NF], bf[NF];
 #pragma unroll
-      for (int a = 0; a < 4; a++) af[a] = Ys[cur][krow * LDSW + wn * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < NF; a++) af[a] = Ys[cur][krow * LDSW + wn * WT + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; b++) bf[b] = Xs[cur][krow * LDSW + wm * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < NF; b++) bf[b] = Xs[cur][krow * LDSW + wm * WT + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; a++)
+      for (int a = 0; a < NF; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = DOps<T>::mfma(af[a], bf[b], acc[a][b]);
+        for (int b = 0; b < NF; b++) acc[a][b] = DOps<T>::mfma(af[a], bf[b], acc[a][b]);
     }
     if (kt + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
@@ -312,13 +319,13 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
 
   double* __restrict__ C = Lm + P.c;
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int a = 0; a < NF; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int m = m0 + wm * 64 + b * 16 + (lane & 15);
+    for (int b = 0; b < NF; b++) {
+      const int m = m0 + wm * WT + b * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int n = n0 + wn * 64 + a * 16 +
+        const int n = n0 + wn * WT + a * 16 +
                       (sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         if (m < P.m && n < P.n && (!P.lower || m >= n)) {
           double* p = C + m + (int64_t)n * ldl;
@@ -328,29 +335,41 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
     }
 }
 
-hipError_t launch_gemm(int prec, double* Lm, int64_t ldl, const void* ws, const GemmProb* probs,
-                       int nprobs, int total_tiles, const double* part, int scale_mode,
-                       DevStatus* st, hipStream_t s) {
-  if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
-  dim3 g(total_tiles), b(256);
+template <int BM>
+static void launch_gemm_bm(int prec, dim3 g, dim3 b, hipStream_t s, double* Lm, int64_t ldl,
+                           const void* ws, const GemmProb* probs, int nprobs, const double* part,
+                           int scale_mode, DevStatus* st) {
   switch (prec) {
     case F16:
-      hipLaunchKernelGGL(k_gemm_q<_Float16>, g, b, 0, s, Lm, ldl, (const _Float16*)ws, probs,
-                         nprobs, part, prec, scale_mode, st);
-      break;
-    case E4M3:
-      hipLaunchKernelGGL(k_gemm_q<unsigned char>, g, b, 0, s, Lm, ldl, (const unsigned char*)ws,
+      hipLaunchKernelGGL((k_gemm_q<_Float16, BM>), g, b, 0, s, Lm, ldl, (const _Float16*)ws,
                          probs, nprobs, part, prec, scale_mode, st);
       break;
+    case E4M3:
+      hipLaunchKernelGGL((k_gemm_q<unsigned char, BM>), g, b, 0, s, Lm, ldl,
+                         (const unsigned char*)ws, probs, nprobs, part, prec, scale_mode, st);
+      break;
     case F32:
-      hipLaunchKernelGGL(k_gemm_d<float>, g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
+      hipLaunchKernelGGL((k_gemm_d<float, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
                          scale_mode, st);
       break;
     default:
-      hipLaunchKernelGGL(k_gemm_d<double>, g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
+      hipLaunchKernelGGL((k_gemm_d<double, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
                          scale_mode, st);
       break;
   }
+}
+
+hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* ws,
+                       const GemmProb* probs, int nprobs, int total_tiles, const double* part,
+                       int scale_mode, DevStatus* st, hipStream_t s) {
+  if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
+  dim3 g(total_tiles), b(256);
+  if (tile == 64)
+    launch_gemm_bm<64>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
+  else if (tile == 128)
+    launch_gemm_bm<128>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

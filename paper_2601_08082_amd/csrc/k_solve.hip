@@ -22,6 +22,14 @@ __device__ inline double coherent_load(const double* p) {
   return __longlong_as_double((long long)v);
 }
 
+// Value of v in lane `src` of the wave (uniform src).
+__device__ inline double bcast(double v, int src) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Wait until *done > k.  Returns false (and flags st->wait_timeout) when the
 // bounded spin gives up, so that every wave always exits.
 __device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* st) {
@@ -46,12 +54,18 @@ __device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* 
 
 // trans = 0: X <- L^{-1} X (forward).  trans = 1: X <- L^{-T} X (backward).
 // ticket[slot] hands out block order, ticket[slot + 1] counts finished blocks.
+// A workgroup stages its diagonal block first, then folds in every earlier
+// block's contribution as soon as that block is published, then solves its
+// diagonal block with one wave (lane = row, readlane broadcasts).  NR is the
+// compile-time number of right-hand sides handled (>= nrhs).
+template <int NR>
 __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restrict__ Lm,
                                               int64_t ldl, int64_t n, int nrhs, double* X,
                                               int64_t ldx, DevStatus* st, int slot) {
-  __shared__ double blk[NB][NB + 1];   // staged 64 x 64 block of L
-  __shared__ double xs[NB][MAXRHS];    // solved block from another workgroup
-  __shared__ double acc[4][NB][MAXRHS];
+  __shared__ double blk[NB][NB + 1];   // staged off-diagonal block, blk[col][row]
+  __shared__ double dg[NB][NB + 1];    // diagonal block, dg[col][row]
+  __shared__ double xs[NB][NR];        // solved block of another workgroup
+  __shared__ double acc[4][NB][NR];
   __shared__ unsigned int my_ticket;
   const int tid = threadIdx.x;
   const int nblk = (int)((n + NB - 1) / NB);
@@ -64,84 +78,102 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
   const int nj = (int)min((int64_t)NB, n - j0);
   const int r = tid & 63, g = tid >> 6;
 
-  double part[MAXRHS];
-  for (int c = 0; c < MAXRHS; c++) part[c] = 0.0;
+  // diagonal block, staged before any waiting
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; u++) {
+    const int idx = tid + 256 * u;
+    const int i = idx & 63, q = idx >> 6;
+    const double v = Lm[(j0 + min(i, nj - 1)) + (j0 + min(q, nj - 1)) * ldl];
+    dg[q][i] = (i < nj && q < nj && i >= q) ? v : 0.0;
+  }
 
-  // contributions of every block solved before this one
+  double part[NR];
+#pragma unroll
+  for (int c = 0; c < NR; c++) part[c] = 0.0;
+
   for (int s = 0; s < t; s++) {
     const int K = trans ? nblk - 1 - s : s;
     const int64_t k0 = (int64_t)K * NB;
     const int nk = (int)min((int64_t)NB, n - k0);
-    // stage L(J, K) (forward) or L(K, J) (backward) while waiting
-    if (!trans) {
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        int i = idx & 63, q = idx >> 6;
-        blk[q][i] = (i < nj && q < nk) ? Lm[(j0 + i) + (k0 + q) * ldl] : 0.0;  // blk[col][row]
-      }
-    } else {
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        int i = idx & 63, q = idx >> 6;
-        blk[q][i] = (i < nk && q < nj) ? Lm[(k0 + i) + (j0 + q) * ldl] : 0.0;  // blk[col][row]
-      }
+    double tmp[NB * NB / 256];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; u++) {
+      const int idx = tid + 256 * u;
+      const int i = idx & 63, q = idx >> 6;
+      double v;
+      if (!trans)
+        v = Lm[(j0 + min(i, nj - 1)) + (k0 + min(q, nk - 1)) * ldl];
+      else
+        v = Lm[(k0 + min(i, nk - 1)) + (j0 + min(q, nj - 1)) * ldl];
+      const bool in = trans ? (i < nk && q < nj) : (i < nj && q < nk);
+      tmp[u] = in ? v : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; u++) {
+      const int idx = tid + 256 * u;
+      blk[idx >> 6][idx & 63] = tmp[u];
     }
     if (!wait_done(done, (unsigned)s, st)) return;
-    for (int idx = tid; idx < NB * nrhs; idx += 256) {
-      int i = idx & 63, c = idx >> 6;
-      xs[i][c] = i < nk ? coherent_load(&X[(k0 + i) + (int64_t)c * ldx]) : 0.0;
+    for (int idx = tid; idx < NB * NR; idx += 256) {
+      const int i = idx % NB, c = idx / NB;
+      xs[i][c] = (i < nk && c < nrhs) ? coherent_load(&X[(k0 + i) + (int64_t)c * ldx]) : 0.0;
     }
     __syncthreads();
     if (!trans) {
       // part[r] += sum_{q = g mod 4} L(j0 + r, k0 + q) x(k0 + q)
       for (int q = g; q < NB; q += 4) {
-        double l = blk[q][r];
-        for (int c = 0; c < nrhs; c++) part[c] += l * xs[q][c];
+        const double l = blk[q][r];
+#pragma unroll
+        for (int c = 0; c < NR; c++) part[c] += l * xs[q][c];
       }
     } else {
       // part[r] += sum_{i = g mod 4} L(k0 + i, j0 + r) x(k0 + i)
       for (int i = g; i < NB; i += 4) {
-        double l = blk[r][i];
-        for (int c = 0; c < nrhs; c++) part[c] += l * xs[i][c];
+        const double l = blk[r][i];
+#pragma unroll
+        for (int c = 0; c < NR; c++) part[c] += l * xs[i][c];
       }
     }
     __syncthreads();
   }
-  for (int c = 0; c < nrhs; c++) acc[g][r][c] = part[c];
-  // diagonal block
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int i = idx & 63, q = idx >> 6;
-    blk[q][i] = (i < nj && q < nj && i >= q) ? Lm[(j0 + i) + (j0 + q) * ldl] : 0.0;
-  }
+#pragma unroll
+  for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
   __syncthreads();
-  for (int idx = tid; idx < NB * nrhs; idx += 256) {
-    int i = idx & 63, c = idx >> 6;
-    double b = i < nj ? X[(j0 + i) + (int64_t)c * ldx] : 0.0;
-    xs[i][c] = b - ((acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]));
-  }
-  __syncthreads();
-  if (!trans) {
-    for (int j = 0; j < nj; j++) {
-      if (tid < nrhs) xs[j][tid] = xs[j][tid] / blk[j][j];
-      __syncthreads();
-      for (int idx = tid; idx < NB * nrhs; idx += 256) {
-        int i = idx & 63, c = idx >> 6;
-        if (i > j && i < nj) xs[i][c] -= blk[j][i] * xs[j][c];
-      }
-      __syncthreads();
+  if (tid < 64) {
+    const int i = tid;
+    double v[NR];
+#pragma unroll
+    for (int c = 0; c < NR; c++) {
+      const double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * ldx] : 0.0;
+      v[c] = b - ((acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]));
     }
-  } else {
-    for (int j = nj - 1; j >= 0; j--) {
-      if (tid < nrhs) xs[j][tid] = xs[j][tid] / blk[j][j];
-      __syncthreads();
-      for (int idx = tid; idx < NB * nrhs; idx += 256) {
-        int i = idx & 63, c = idx >> 6;
-        if (i < j) xs[i][c] -= blk[i][j] * xs[j][c];   // L(j, i) = blk[i][j]
+    const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;   // lane i: 1 / L(i, i)
+    if (!trans) {
+      for (int j = 0; j < nj; j++) {
+        const double lij = dg[j][i];             // L(i, j)
+        const double ij = bcast(inv, j);
+#pragma unroll
+        for (int c = 0; c < NR; c++) {
+          const double xj = bcast(v[c], j) * ij;
+          const double upd = v[c] - lij * xj;
+          v[c] = i == j ? xj : (i > j ? upd : v[c]);
+        }
       }
-      __syncthreads();
+    } else {
+      for (int j = nj - 1; j >= 0; j--) {
+        const double lji = dg[i][j];             // L(j, i) for i < j
+        const double ij = bcast(inv, j);
+#pragma unroll
+        for (int c = 0; c < NR; c++) {
+          const double xj = bcast(v[c], j) * ij;
+          const double upd = v[c] - lji * xj;
+          v[c] = i == j ? xj : (i < j ? upd : v[c]);
+        }
+      }
     }
-  }
-  for (int idx = tid; idx < NB * nrhs; idx += 256) {
-    int i = idx & 63, c = idx >> 6;
-    if (i < nj) X[(j0 + i) + (int64_t)c * ldx] = xs[i][c];
+#pragma unroll
+    for (int c = 0; c < NR; c++)
+      if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * ldx] = v[c];
   }
   __threadfence();
   __syncthreads();
@@ -261,8 +293,17 @@ hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int 
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (nrhs > MAXRHS || (ticket_slot != 0 && ticket_slot != 2)) return hipErrorInvalidValue;
   int nblk = (int)((n + NB - 1) / NB);
-  hipLaunchKernelGGL(k_trsv, dim3(nblk), dim3(256), 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st,
-                     ticket_slot);
+  dim3 g(nblk), b(256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_trsv<1>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
+  else if (nrhs <= 2)
+    hipLaunchKernelGGL(k_trsv<2>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL(k_trsv<4>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL(k_trsv<8>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
+  else
+    hipLaunchKernelGGL(k_trsv<16>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
   return hipGetLastError();
 }
 

@@ -11,9 +11,11 @@
 //    (disjoint outputs, read-only operand panel), so each Tree-SYRK becomes one
 //    max-abs launch, one cast launch and one grouped GEMM launch per precision;
 //  - Tree-TRSM is a chain (each GEMM consumes the previous leaf solve);
-//  - a leaf of the precision tree larger than the kernel leaf (64) is factored
-//    / solved by an all-leaf-precision sub-recursion down to 64; this is a
-//    leaf-precision Cholesky (resp. triangular solve) of that leaf.
+//  - a leaf of the precision tree larger than the kernel leaf (128) is factored
+//    / solved by an all-leaf-precision sub-recursion down to 128; this is a
+//    leaf-precision Cholesky (resp. triangular solve) of that leaf;
+//  - GEMM launches use 128 x 128 output tiles, or 64 x 64 when 128-tiles would
+//    leave most of the 256 compute units idle.
 #include "plan.h"
 
 #include <algorithm>
@@ -153,8 +155,6 @@ struct Builder {
       g.n = nd.n;
       g.k = nd.k;
       g.lower = nd.lower;
-      g.tiles_m = (int)cdiv(nd.m, 128);
-      g.tiles_n = (int)cdiv(nd.n, 128);
       std::pair<int, int> px{0, 0}, py{0, 0};
       if (with_parts) {
         px = add_maxabs(mj, nd.xr, nd.xc, nd.m, nd.k);
@@ -214,8 +214,17 @@ struct Builder {
       Launch L{Launch::GEMM, prec};
       L.first = (int)P.gemms.size();
       L.count = (int)gp.size();
+      // 128 x 128 tiles unless that leaves most of the 256 CUs idle
+      int64_t t128 = 0;
+      for (auto& g : gp) {
+        int64_t tm = cdiv(g.m, 128);
+        t128 += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, 128);
+      }
+      L.tile = t128 >= 256 ? 128 : 64;
       int tiles = 0;
       for (auto& g : gp) {
+        g.tiles_m = (int)cdiv(g.m, L.tile);
+        g.tiles_n = (int)cdiv(g.n, L.tile);
         g.tile_start = tiles;
         tiles += g.lower ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
       }

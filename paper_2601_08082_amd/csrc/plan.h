@@ -16,6 +16,7 @@ struct Launch {
   int prec;
   int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF: i0, m; TRSM: r0, m, c0, k
   int first = 0, count = 0, total = 0;    // descriptor range, workgroups
+  int tile = 128;                         // GEMM output tile (64 or 128)
 };
 
 struct PlanStats {

@@ -7,9 +7,12 @@ Bars (derived in the design notes):
   * FP64 tree: ||A - L L^T||_F / ||A||_F <= 1e-13 and
     ||L - L_oracle||_F / ||L_oracle||_F <= 4 n u64 kappa-free bound 1e-13;
   * mixed trees: backward error within a factor 2 of the oracle's emulation of
-    the same tree, and ||L - L_emu|| at most a quarter of ||L_emu - L_64|| (the
-    two differ only in FP32 accumulation order, far below the quantization
-    error they share);
+    the same tree, and, with FP64 leaves, ||L - L_emu|| at most a quarter of
+    ||L_emu - L_64|| (the two differ only in FP32 accumulation order, far below
+    the operand quantization error they share).  With FP32 leaves the FP32
+    rounding of the leaf arithmetic itself dominates and its order differs
+    (blocked MFMA updates vs. one product at a time), so there the bar is
+    ||L - L_emu|| <= 2 ||L_emu - L_64||;
   * casts: bit-identical codes and scale.
 """
 import math
@@ -147,7 +150,8 @@ def test_mixed_tree_vs_emulation(M, ctx, name, n, ratio, shift, kw):
     assert 0.5 <= be_gpu / be_emu <= 2.0, (be_gpu, be_emu)
     d_ge = np.linalg.norm(np.tril(L) - np.tril(Le))
     d_e64 = np.linalg.norm(np.tril(Le) - np.tril(L64))
-    assert d_ge <= 0.25 * d_e64, (d_ge, d_e64)
+    bar = 2.0 if t.leaf_prec == M.F32 else 0.25
+    assert d_ge <= bar * d_e64, (d_ge, d_e64)
 
 
 def test_node_precision_policy_applied(M, ctx):
