@@ -143,14 +143,28 @@ int mpchol_solve(mpchol_ctx ctx, int64_t n, int64_t nrhs, const double* A, int64
                  void* stream, mpchol_info* info);
 
 /*
- * Factor and solve `batch` independent SPD systems of uneven sizes.
+ * Factor and solve `batch` independent SPD systems of uneven sizes with ONE
+ * persistent kernel launch (captured once into a hipGraph and replayed while
+ * the arguments stay the same): one workgroup per compute unit pulls systems
+ * from a device work queue, largest first, runs that system's plan
+ * (Algorithms 1-3 with the tree's layering and quantization), then the
+ * substitution solve and the FP64-residual refinement of mpchol_solve, all
+ * on the device.
  *   n_host[i], lda_host[i], ldl_host[i]   host arrays of sizes and strides.
- *   A_dev[i], L_dev[i], B_dev[i], X_dev[i]  host arrays of device pointers.
- *   nrhs        right-hand sides per system (B_i, X_i are n_i x nrhs, leading
- *               dimension n_i).
- *   tol, max_iter  refinement rule of mpchol_solve, per system.
- *   tree        descriptor shared by all systems (leaf/split used as given).
- *   info_host   host array of batch mpchol_info, filled after synchronizing.
+ *   A_dev[i], L_dev[i], B_dev[i], X_dev[i]  host arrays of device pointers;
+ *               L_dev[i] may equal A_dev[i] only when nrhs = 0 (then ldl must
+ *               equal lda): the refinement reads A in FP64.
+ *   nrhs        right-hand sides per system, 0..16 (B_i, X_i are n_i x nrhs,
+ *               leading dimension n_i); 0: factor only.
+ *   tol, max_iter  the refinement rule of mpchol_solve, per system.
+ *   tree        descriptor shared by all systems; its leaf is replaced per
+ *               system by the context's tune table (mpchol_set_tune_table).
+ *   info_host   NULL or host array of batch mpchol_info (status, failed
+ *               index, refinement steps, last correction; ms_factor = the
+ *               whole launch).
+ * Synchronizes the stream.  Returns the largest status code over the systems.
+ * Errors: -2 batch < 0; -3 n_host / a size outside 1..2^20; -4 A_dev; -5 lda;
+ * -6 L_dev (NULL, or equal to A_dev with nrhs > 0); -7 ldl; -8 nrhs; -9 B_dev / X_dev; -12 max_iter; -13 descriptor.
  */
 int mpchol_factor_batched(mpchol_ctx ctx, int64_t batch, const int64_t* n_host,
                           const double* const* A_dev, const int64_t* lda_host,
@@ -199,7 +213,9 @@ enum {
   MPCHOL_PROF_MAXABS = 5,     /* block max-abs reductions  */
   MPCHOL_PROF_POTRF = 6,      /* leaf POTRF                */
   MPCHOL_PROF_TRSM = 7,       /* leaf TRSM                 */
-  MPCHOL_PROF_KINDS = 8
+  MPCHOL_PROF_TRSV = 8,       /* triangular solves of mpchol_solve (work: bytes of L read) */
+  MPCHOL_PROF_RESIDUAL = 9,   /* FP64 residuals of mpchol_solve (work: bytes of A read)    */
+  MPCHOL_PROF_KINDS = 10
 };
 /* mpchol_profile: clear the accumulators and record a HIP event pair around
  * every later launch whose class bit is set in kind_mask (0 = off).  Events go
@@ -209,6 +225,16 @@ enum {
  * number of launches.  Arrays have MPCHOL_PROF_KINDS entries (NULL: skip). */
 int mpchol_profile(mpchol_ctx ctx, uint32_t kind_mask);
 int mpchol_profile_read(mpchol_ctx ctx, double* ms, double* work, int64_t* launches);
+
+/*
+ * Leaf size by system size for mpchol_factor_batched (the autotuner's
+ * output): a system of order n uses leaf[i] for the first i with
+ * n <= nmax[i] (nmax strictly increasing), the descriptor's leaf above the
+ * last entry.  count 0 clears the table.  Copies the arrays.
+ * Errors: -2 count < 0; -3 nmax NULL or not increasing; -4 a leaf < 1.
+ */
+int mpchol_set_tune_table(mpchol_ctx ctx, int32_t count, const int32_t* nmax,
+                          const int32_t* leaf);
 
 /* Human-readable build/version string (static storage). */
 const char* mpchol_version(void);

@@ -6,11 +6,13 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <sstream>
 #include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/mpchol.h"
+#include "batched.h"
 #include "internal.h"
 #include "numfmt.h"
 #include "plan.h"
@@ -51,7 +53,34 @@ struct mpchol_ctx_s {
   double acc_ms[MPCHOL_PROF_KINDS] = {0};
   double acc_work[MPCHOL_PROF_KINDS] = {0};
   int64_t acc_n[MPCHOL_PROF_KINDS] = {0};
+  // leaf choice by size for the batched path (mpchol_set_tune_table)
+  std::vector<int32_t> tune_nmax, tune_leaf;
+  // batched program cache: device arrays and the captured graph of the last call
+  struct Batch {
+    std::string key;
+    std::vector<void*> bufs;        // device allocations owned by the program
+    BatchProgram prog{};
+    BatchInfo* hinfo = nullptr;     // pinned
+    int64_t batch = 0;
+    int nwg = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap = nullptr;
+  } bt;
 };
+
+static void free_batch(mpchol_ctx c) {
+  auto& B = c->bt;
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  for (void* p : B.bufs) (void)hipFree(p);
+  B.bufs.clear();
+  if (B.hinfo) (void)hipHostFree(B.hinfo);
+  B.hinfo = nullptr;
+  B.key.clear();
+}
 
 static int launch_kind(const Launch& L) {
   switch (L.kind) {
@@ -229,6 +258,22 @@ static int status_from(const DevStatus& h, mpchol_info* info) {
   return st;
 }
 
+static int32_t tuned_leaf(mpchol_ctx c, int64_t n, int32_t dflt) {
+  for (size_t i = 0; i < c->tune_nmax.size(); i++)
+    if (n <= c->tune_nmax[i]) return c->tune_leaf[i];
+  return dflt;
+}
+
+template <typename T>
+static int dev_upload(std::vector<void*>& keep, T** dptr, const std::vector<T>& v) {
+  *dptr = nullptr;
+  size_t bytes = sizeof(T) * std::max<size_t>(v.size(), 1);
+  HIPCHK(hipMalloc((void**)dptr, bytes));
+  keep.push_back(*dptr);
+  if (!v.empty()) HIPCHK(hipMemcpy(*dptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return 0;
+}
+
 extern "C" {
 
 const char* mpchol_version(void) { return "mpchol 0.1 (gfx950, HIP)"; }
@@ -265,6 +310,8 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  free_batch(c);
+  if (c->bt.cap) (void)hipStreamDestroy(c->bt.cap);
   delete c;
   return 0;
 }
@@ -307,11 +354,16 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
 // X <- L^-T L^-1 X for up to kMaxRhs columns at a time.
 static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
+  const double lbytes = (double)n * (n + 1) / 2 * 8.0;
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     HIPCHK(launch_ticket_reset(c->dst, s));
+    int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
     HIPCHK(launch_trsv(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 0, s));
+    prof_end(c, pk, s);
+    pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
     HIPCHK(launch_trsv(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 2, s));
+    prof_end(c, pk, s);
   }
   return 0;
 }
@@ -357,8 +409,11 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
     for (int it = 1; it <= max_iter; it++) {
       for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
         int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
+        int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_RESIDUAL,
+                                           (double)n * (n + 1) / 2 * 8.0, s) : -1;
         HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
                                s));
+        prof_end(c, pk, s);
       }
       r = chol_solve_inplace(c, n, nrhs, L, ldl, R, n, s);
       if (r) return r;
@@ -415,6 +470,20 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
   return status;
 }
 
+int mpchol_set_tune_table(mpchol_ctx c, int32_t count, const int32_t* nmax,
+                          const int32_t* leaf) {
+  if (!c) return -1;
+  if (count < 0) return -2;
+  if (count > 0 && (!nmax || !leaf)) return -3;
+  for (int32_t i = 0; i < count; i++) {
+    if (leaf[i] < 1) return -4;
+    if (i > 0 && nmax[i] <= nmax[i - 1]) return -3;
+  }
+  c->tune_nmax.assign(nmax, nmax + count);
+  c->tune_leaf.assign(leaf, leaf + count);
+  return 0;
+}
+
 int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
                           const double* const* A_dev, const int64_t* lda_host,
                           double* const* L_dev, const int64_t* ldl_host, int64_t nrhs,
@@ -423,28 +492,180 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
                           mpchol_info* info_host) {
   if (!c) return -1;
   if (batch < 0) return -2;
-  if (batch > 0 && (!n_host || !A_dev || !lda_host || !L_dev || !ldl_host)) return -3;
+  if (batch > 0 && !n_host) return -3;
+  if (batch > 0 && !A_dev) return -4;
+  if (batch > 0 && !lda_host) return -5;
+  if (batch > 0 && !L_dev) return -6;
+  if (batch > 0 && !ldl_host) return -7;
+  if (nrhs < 0 || nrhs > kMaxRhs) return -8;
+  if (nrhs > 0 && (!B_dev || !X_dev)) return -9;
+  if (max_iter < 0) return -12;
   int v = validate_tree(tree);
-  if (v) return v;
+  if (v) return v == -7 ? -13 : v;
+  for (int64_t i = 0; i < batch; i++) {
+    if (n_host[i] < 1 || n_host[i] > (1 << 20)) return -3;
+    if (!A_dev[i] || !L_dev[i]) return -4;
+    if (lda_host[i] < n_host[i]) return -5;
+    if (ldl_host[i] < n_host[i]) return -7;
+    if (L_dev[i] == A_dev[i] && ldl_host[i] != lda_host[i]) return -7;
+    if (nrhs > 0 && L_dev[i] == A_dev[i]) return -6;   // refinement needs A in FP64
+    if (nrhs > 0 && (!B_dev[i] || !X_dev[i])) return -9;
+  }
+  if (info_host) std::memset(info_host, 0, sizeof(mpchol_info) * (size_t)batch);
+  if (batch == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  auto& BT = c->bt;
+
+  // cache key: everything the device program depends on
+  std::ostringstream key;
+  key << batch << '|' << nrhs << '|' << tol << '|' << max_iter << '|' << plan_key(0, 1, tree);
+  for (size_t i = 0; i < c->tune_nmax.size(); i++) key << c->tune_nmax[i] << ':' << c->tune_leaf[i] << ',';
+  for (int64_t i = 0; i < batch; i++) {
+    key << '|' << n_host[i] << ',' << lda_host[i] << ',' << ldl_host[i] << ',' << (const void*)A_dev[i]
+        << ',' << (const void*)L_dev[i];
+    if (nrhs > 0) key << ',' << (const void*)B_dev[i] << ',' << (const void*)X_dev[i];
+  }
+  if (BT.key != key.str()) {
+    HIPCHK(hipDeviceSynchronize());
+    free_batch(c);
+    std::vector<BatchTask> tasks;
+    std::vector<MaxabsJob> mj;
+    std::vector<CastJob> cj;
+    std::vector<GemmProb> gp;
+    std::vector<BatchMat> mats((size_t)batch);
+    std::map<std::string, std::pair<int32_t, int32_t>> seen;  // plan -> task range
+    size_t ws_max = 256;
+    int64_t parts_max = 1;
+    for (int64_t i = 0; i < batch; i++) {
+      mpchol_tree t = *tree;
+      t.leaf = tuned_leaf(c, n_host[i], tree->leaf);
+      std::string pk = plan_key(n_host[i], ldl_host[i], &t);
+      auto it = seen.find(pk);
+      if (it == seen.end()) {
+        Plan P;
+        build_plan(P, n_host[i], ldl_host[i], &t, true);
+        int32_t t0 = (int32_t)tasks.size();
+        for (const Launch& L : P.launches) {
+          BatchTask T{};
+          T.kind = (int32_t)L.kind;
+          T.prec = L.prec;
+          T.tile = L.tile;
+          T.count = L.count;
+          T.total = L.total;
+          T.a0 = L.a0;
+          T.a1 = L.a1;
+          T.a2 = L.a2;
+          T.a3 = L.a3;
+          if (L.kind == Launch::MAXABS) {
+            T.first = (int32_t)mj.size();
+            mj.insert(mj.end(), P.maxabs.begin() + L.first, P.maxabs.begin() + L.first + L.count);
+          } else if (L.kind == Launch::CAST) {
+            T.first = (int32_t)cj.size();
+            cj.insert(cj.end(), P.casts.begin() + L.first, P.casts.begin() + L.first + L.count);
+          } else if (L.kind == Launch::GEMM) {
+            T.first = (int32_t)gp.size();
+            gp.insert(gp.end(), P.gemms.begin() + L.first, P.gemms.begin() + L.first + L.count);
+          }
+          tasks.push_back(T);
+        }
+        ws_max = std::max(ws_max, P.ws_bytes);
+        parts_max = std::max(parts_max, P.parts);
+        it = seen.emplace(pk, std::make_pair(t0, (int32_t)tasks.size())).first;
+      }
+      BatchMat& M = mats[(size_t)i];
+      M.A = A_dev[i];
+      M.L = L_dev[i];
+      M.B = nrhs > 0 ? B_dev[i] : nullptr;
+      M.X = nrhs > 0 ? X_dev[i] : nullptr;
+      M.lda = lda_host[i];
+      M.ldl = ldl_host[i];
+      M.n = (int32_t)n_host[i];
+      M.t0 = it->second.first;
+      M.t1 = it->second.second;
+    }
+    std::vector<int32_t> order((size_t)batch);
+    for (int64_t i = 0; i < batch; i++) order[(size_t)i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return n_host[a] > n_host[b]; });
+    int64_t nmax = 0;
+    for (int64_t i = 0; i < batch; i++) nmax = std::max(nmax, n_host[i]);
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, batch));
+    BatchProgram& G = BT.prog;
+    G = BatchProgram{};
+    if (dev_upload(BT.bufs, (BatchTask**)&G.tasks, tasks) ||
+        dev_upload(BT.bufs, (MaxabsJob**)&G.maxabs, mj) ||
+        dev_upload(BT.bufs, (CastJob**)&G.casts, cj) ||
+        dev_upload(BT.bufs, (GemmProb**)&G.gemms, gp) ||
+        dev_upload(BT.bufs, (BatchMat**)&G.mats, mats) ||
+        dev_upload(BT.bufs, (int32_t**)&G.order, order)) {
+      free_batch(c);
+      return MPCHOL_HIP_ERROR;
+    }
+    G.ws_stride = (ws_max + 255) / 256 * 256;
+    G.part_stride = (size_t)parts_max;
+    G.scratch_stride = (size_t)(nmax * std::max<int64_t>(nrhs, 1));
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(BatchInfo) * (size_t)batch));
+    BT.bufs.push_back(p);
+    G.info = (BatchInfo*)p;
+    HIPCHK(hipMalloc(&p, 256));
+    BT.bufs.push_back(p);
+    G.queue = (unsigned int*)p;
+    HIPCHK(hipMalloc(&p, G.ws_stride * (size_t)nwg));
+    BT.bufs.push_back(p);
+    G.ws = (char*)p;
+    HIPCHK(hipMalloc(&p, sizeof(double) * G.part_stride * (size_t)nwg));
+    BT.bufs.push_back(p);
+    G.part = (double*)p;
+    HIPCHK(hipMalloc(&p, sizeof(double) * G.scratch_stride * (size_t)nwg));
+    BT.bufs.push_back(p);
+    G.scratch = (double*)p;
+    HIPCHK(hipMalloc(&p, sizeof(DevStatus) * (size_t)nwg));
+    BT.bufs.push_back(p);
+    G.status = (DevStatus*)p;
+    G.batch = (int32_t)batch;
+    G.nrhs = (int32_t)nrhs;
+    G.max_iter = max_iter;
+    G.scale_mode = tree->scale_mode;
+    G.tol = tol;
+    HIPCHK(hipHostMalloc((void**)&BT.hinfo, sizeof(BatchInfo) * (size_t)batch,
+                         hipHostMallocDefault));
+    BT.batch = batch;
+    BT.nwg = nwg;
+    // one graph: queue reset + persistent kernel + status copy-back
+    if (!BT.cap) HIPCHK(hipStreamCreateWithFlags(&BT.cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(BT.cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batched(G, nwg, BT.cap);
+    hipError_t me = hipMemcpyAsync(BT.hinfo, G.info, sizeof(BatchInfo) * (size_t)batch,
+                                   hipMemcpyDeviceToHost, BT.cap);
+    hipError_t ee = hipStreamEndCapture(BT.cap, &BT.graph);
+    if (le != hipSuccess || me != hipSuccess || ee != hipSuccess) {
+      free_batch(c);
+      return MPCHOL_HIP_ERROR;
+    }
+    HIPCHK(hipGraphInstantiate(&BT.exec, BT.graph, nullptr, nullptr, 0));
+    BT.key = key.str();
+  }
+  HIPCHK(hipEventRecord(c->ev0, s));
+  HIPCHK(hipGraphLaunch(BT.exec, s));
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   int worst = 0;
   for (int64_t i = 0; i < batch; i++) {
-    mpchol_info fi{}, si{};
-    int r = mpchol_factor(c, n_host[i], A_dev[i], lda_host[i], L_dev[i], ldl_host[i], tree,
-                          stream, &fi);
-    if (r < 0) return r;
-    if (r == 0 && nrhs > 0 && B_dev && X_dev) {
-      r = mpchol_solve(c, n_host[i], nrhs, A_dev[i], lda_host[i], L_dev[i], ldl_host[i], B_dev[i],
-                       n_host[i], X_dev[i], n_host[i], tol, max_iter, stream, &si);
-      if (r < 0) return r;
-    }
+    const BatchInfo& I = BT.hinfo[i];
     if (info_host) {
-      info_host[i] = fi;
-      info_host[i].ir_iters = si.ir_iters;
-      info_host[i].final_rel_corr = si.final_rel_corr;
-      info_host[i].ms_solve = si.ms_solve;
-      if (fi.status == 0) info_host[i].status = si.status;
+      info_host[i].status = I.status;
+      info_host[i].ir_iters = I.ir_iters;
+      info_host[i].failed_index = I.failed_index;
+      info_host[i].final_rel_corr = I.final_rel_corr;
+      info_host[i].ms_factor = ms;
     }
-    worst = std::max(worst, r);
+    worst = std::max(worst, (int)I.status);
   }
   return worst;
 }

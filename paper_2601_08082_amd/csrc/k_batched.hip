@@ -1,0 +1,418 @@
+// Persistent batched factor + refined solve of many independent SPD systems
+// of uneven sizes: one launch, one workgroup per compute unit, a device work
+// queue over the systems (largest first).  A workgroup takes a system, copies
+// its lower triangle, runs that system's plan (the same Tree-POTRF /
+// Tree-TRSM / Tree-SYRK task list the single-matrix path launches, Algorithms
+// 1-3 with the Section 3.3 layering and Section 3.4 quantization) with the
+// workgroup-level kernel bodies, then solves and refines in FP64 on its own:
+// x0 = L^-T L^-1 b; r = b - A x; d = L^-T L^-1 r; x += d until
+// max_col ||d||_inf <= tol ||x||_inf, max_iter steps, or growth twice in a row.
+// Every wave leaves the queue loop once the counter passes the batch size.
+//
+// Compiled without FP contraction (the leaf bodies require it).
+#include "batched.h"
+#include "dev_gemm.h"
+#include "dev_leaf.h"
+#include "dev_quant.h"
+
+namespace mpc {
+
+namespace {
+
+constexpr int kPool = trsm_leaf_lds_bytes<double>();  // largest body
+static_assert(kPool >= potrf_leaf_lds_bytes<double>(), "pool");
+static_assert(kPool >= gemm_q_lds_bytes<_Float16, 128>(), "pool");
+static_assert(kPool >= gemm_d_lds_bytes<double, 128>(), "pool");
+
+__device__ inline int find_job_max(const MaxabsJob* j, int nj, int w) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (j[mid].wg_start <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_job_cast(const CastJob* j, int nj, int w) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (j[mid].wg_start <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline double wg_bcast(double v, int src) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// blk[col][row] = M(r0 + row, c0 + col) for a 64 x 64 block (zero outside
+// rows < nr, cols < nc); lanes run along rows (coalesced).
+__device__ inline void stage_block(double (*blk)[65], const double* __restrict__ M, int64_t ld,
+                                   int r0, int c0, int nr, int nc) {
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int i = idx & 63, q = idx >> 6;
+    blk[q][i] = (i < nr && q < nc) ? M[(r0 + i) + (int64_t)(c0 + q) * ld] : 0.0;
+  }
+}
+
+// X <- L^-1 X (trans 0) or L^-T X (trans 1), n x nrhs (ld n), one workgroup,
+// 64-row blocks.  pool: blk, dg [64][65] + acc[4][64][16] doubles.
+__device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, int64_t ldl, int n, int nrhs,
+                        double* X, char* pool) {
+  typedef double Col[65];
+  Col* blk = reinterpret_cast<Col*>(pool);                             // blk[col][row]
+  Col* dg = blk + 64;                                                  // dg[col][row]
+  double* acc = reinterpret_cast<double*>(pool + 2 * 64 * 65 * 8);     // [4][64][16]
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+  const int nb = (n + 63) / 64;
+  for (int s = 0; s < nb; s++) {
+    const int J = trans ? nb - 1 - s : s;
+    const int j0 = J * 64, nj = min(64, n - j0);
+    double part[16];
+    for (int c = 0; c < 16; c++) part[c] = 0.0;
+    for (int u = 0; u < s; u++) {
+      const int K = trans ? nb - 1 - u : u;
+      const int k0 = K * 64, nk = min(64, n - k0);
+      __syncthreads();
+      if (!trans) stage_block(blk, L, ldl, j0, k0, nj, nk);   // L(J, K)
+      else stage_block(blk, L, ldl, k0, j0, nk, nj);          // L(K, J)
+      __syncthreads();
+      if (!trans) {
+        for (int q = g; q < nk; q += 4) {
+          const double l = blk[q][r];
+          for (int c = 0; c < nrhs; c++) part[c] += l * X[(k0 + q) + (int64_t)c * n];
+        }
+      } else {
+        for (int i = g; i < nk; i += 4) {
+          const double l = blk[r][i];
+          for (int c = 0; c < nrhs; c++) part[c] += l * X[(k0 + i) + (int64_t)c * n];
+        }
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < nrhs; c++) acc[(g * 64 + r) * 16 + c] = part[c];
+    stage_block(dg, L, ldl, j0, j0, nj, nj);
+    __syncthreads();
+    if (tid < 64) {
+      const int i = tid;
+      double v[16];
+      for (int c = 0; c < 16; c++) {
+        double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * n] : 0.0;
+        v[c] = c < nrhs ? b - ((acc[(0 * 64 + i) * 16 + c] + acc[(1 * 64 + i) * 16 + c]) +
+                               (acc[(2 * 64 + i) * 16 + c] + acc[(3 * 64 + i) * 16 + c]))
+                        : 0.0;
+      }
+      const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;
+      for (int jj = 0; jj < nj; jj++) {
+        const int j = trans ? nj - 1 - jj : jj;
+        const double lij = trans ? dg[i][j] : dg[j][i];   // L(j, i) resp. L(i, j)
+        const double ij = wg_bcast(inv, j);
+        for (int c = 0; c < nrhs; c++) {
+          const double xj = wg_bcast(v[c], j) * ij;
+          const double upd = v[c] - lij * xj;
+          const bool below = trans ? (i < j) : (i > j);
+          v[c] = i == j ? xj : (below ? upd : v[c]);
+        }
+      }
+      for (int c = 0; c < nrhs; c++)
+        if (i < nj) X[(j0 + i) + (int64_t)c * n] = v[c];
+    }
+    __syncthreads();
+  }
+}
+
+// R = B - A X (A symmetric, lower stored), one workgroup, 64 x 64 blocks
+// staged through LDS.
+__device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t lda, int n, int nrhs,
+                            const double* X, const double* B, int64_t ldb, double* R,
+                            char* pool) {
+  typedef double Col[65];
+  Col* blk = reinterpret_cast<Col*>(pool);                          // blk[q][r] = A_sym(i0 + r, j0 + q)
+  double* acc = reinterpret_cast<double*>(pool + 64 * 65 * 8);     // [4][64][16]
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+  const int nb = (n + 63) / 64;
+  for (int I = 0; I < nb; I++) {
+    const int i0 = I * 64, ni = min(64, n - i0);
+    double part[16];
+    for (int c = 0; c < 16; c++) part[c] = 0.0;
+    for (int J = 0; J < nb; J++) {
+      const int j0 = J * 64, nj = min(64, n - j0);
+      __syncthreads();
+      if (J < I) {
+        stage_block(blk, A, lda, i0, j0, ni, nj);
+      } else if (J > I) {
+        for (int idx = tid; idx < 64 * 64; idx += 256) {   // A(j0 + q, i0 + r), lanes along q
+          const int q = idx & 63, rr = idx >> 6;
+          blk[q][rr] = (rr < ni && q < nj) ? A[(j0 + q) + (int64_t)(i0 + rr) * lda] : 0.0;
+        }
+      } else {
+        for (int idx = tid; idx < 64 * 64; idx += 256) {
+          const int i = idx & 63, q = idx >> 6;
+          double v = 0.0;
+          if (i < ni && q < nj)
+            v = i >= q ? A[(i0 + i) + (int64_t)(j0 + q) * lda] : A[(j0 + q) + (int64_t)(i0 + i) * lda];
+          blk[q][i] = v;
+        }
+      }
+      __syncthreads();
+      for (int q = g; q < nj; q += 4) {
+        const double a = blk[q][r];
+        for (int c = 0; c < nrhs; c++) part[c] += a * X[(j0 + q) + (int64_t)c * n];
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < nrhs; c++) acc[(g * 64 + r) * 16 + c] = part[c];
+    __syncthreads();
+    for (int idx = tid; idx < 64 * nrhs; idx += 256) {
+      const int ii = idx & 63, c = idx >> 6;
+      if (ii < ni) {
+        const double t = (acc[(0 * 64 + ii) * 16 + c] + acc[(1 * 64 + ii) * 16 + c]) +
+                         (acc[(2 * 64 + ii) * 16 + c] + acc[(3 * 64 + ii) * 16 + c]);
+        R[(i0 + ii) + (int64_t)c * n] = B[(i0 + ii) + (int64_t)c * ldb] - t;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// X += D; returns max over columns of ||D||_inf / ||X||_inf (Inf if non-finite).
+__device__ double wg_update(int n, int nrhs, double* X, const double* D, char* pool) {
+  double* red = reinterpret_cast<double*>(pool);
+  const int tid = threadIdx.x;
+  double worst = 0.0;
+  for (int c = 0; c < nrhs; c++) {
+    double dm = 0.0, xm = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      const double d = D[i + (int64_t)c * n];
+      const double x = X[i + (int64_t)c * n] + d;
+      X[i + (int64_t)c * n] = x;
+      double ad = fabs(d), ax = fabs(x);
+      if (!(ad <= 1.7976931348623157e308)) ad = __longlong_as_double(0x7FF0000000000000ll);
+      if (!(ax <= 1.7976931348623157e308)) ax = __longlong_as_double(0x7FF0000000000000ll);
+      dm = fmax(dm, ad);
+      xm = fmax(xm, ax);
+    }
+    __syncthreads();
+    red[tid] = dm;
+    red[256 + tid] = xm;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        red[tid] = fmax(red[tid], red[tid + s]);
+        red[256 + tid] = fmax(red[256 + tid], red[256 + tid + s]);
+      }
+      __syncthreads();
+    }
+    const double rr = red[256] > 0.0 ? red[0] / red[256] : red[0];
+    worst = fmax(worst, (rr == rr) ? rr : __longlong_as_double(0x7FF0000000000000ll));
+    __syncthreads();
+  }
+  return worst;
+}
+
+// Non-inlined entry points: each body keeps its own register allocation
+// inside the single persistent kernel.
+template <typename Q, int BM>
+__device__ __noinline__ void nb_gemm_q(double* L, int64_t ldl, const Q* ws, const GemmProb* P,
+                                       int t, const double* part, int prec, int sm,
+                                       DevStatus* st, char* pool) {
+  gemm_q_tile<Q, BM>(L, ldl, ws, *P, t, part, prec, sm, st, pool);
+}
+template <typename T, int BM>
+__device__ __noinline__ void nb_gemm_d(double* L, int64_t ldl, const GemmProb* P, int t,
+                                       const double* part, int prec, int sm, DevStatus* st,
+                                       char* pool) {
+  gemm_d_tile<T, BM>(L, ldl, *P, t, part, prec, sm, st, pool);
+}
+template <typename T>
+__device__ __noinline__ void nb_potrf(double* L, int64_t ldl, int64_t i0, int m, DevStatus* st,
+                                      char* pool) {
+  potrf_leaf_body<T>(L, ldl, i0, m, st, pool);
+}
+template <typename T>
+__device__ __noinline__ void nb_trsm(double* L, int64_t ldl, int64_t r0, int64_t m, int64_t c0,
+                                     int k, int rb, char* pool) {
+  trsm_leaf_rows<T>(L, ldl, r0, m, c0, k, rb, pool);
+}
+template <typename Q>
+__device__ __noinline__ void nb_cast(const double* L, int64_t ldl, const CastJob* jb, int t,
+                                     const double* part, int prec, int sm, Q* ws, DevStatus* st,
+                                     char* pool) {
+  cast_tile<Q>(L, ldl, *jb, t, part, prec, sm, ws, st, pool);
+}
+__device__ __noinline__ void nb_maxabs(const double* L, int64_t ldl, const MaxabsJob* jb, int w,
+                                       double* part, double* red) {
+  maxabs_part(L, ldl, *jb, w, part, red);
+}
+
+__device__ void run_task(const BatchTask& T, const BatchProgram& prog, double* L, int64_t ldl,
+                         char* ws, double* part, DevStatus* st, int scale_mode, char* pool) {
+  switch (T.kind) {
+    case BatchTask::POTRF:
+      if (T.prec == F32) nb_potrf<float>(L, ldl, T.a0, (int)T.a1, st, pool);
+      else nb_potrf<double>(L, ldl, T.a0, (int)T.a1, st, pool);
+      break;
+    case BatchTask::TRSM: {
+      const int nrb = (int)((T.a1 + 63) / 64);
+      for (int rb = 0; rb < nrb; rb++) {
+        if (T.prec == F32) nb_trsm<float>(L, ldl, T.a0, T.a1, T.a2, (int)T.a3, rb, pool);
+        else nb_trsm<double>(L, ldl, T.a0, T.a1, T.a2, (int)T.a3, rb, pool);
+      }
+      break;
+    }
+    case BatchTask::MAXABS: {
+      const MaxabsJob* jobs = prog.maxabs + T.first;
+      for (int w = 0; w < T.total; w++) {
+        const MaxabsJob& jb = jobs[find_job_max(jobs, T.count, w)];
+        nb_maxabs(L, ldl, &jb, w - jb.wg_start, part, reinterpret_cast<double*>(pool));
+      }
+      break;
+    }
+    case BatchTask::CAST: {
+      const CastJob* jobs = prog.casts + T.first;
+      for (int w = 0; w < T.total; w++) {
+        const CastJob& jb = jobs[find_job_cast(jobs, T.count, w)];
+        if (T.prec == F16)
+          nb_cast<_Float16>(L, ldl, &jb, w - jb.wg_start, part, T.prec, scale_mode,
+                            reinterpret_cast<_Float16*>(ws), st, pool);
+        else
+          nb_cast<unsigned char>(L, ldl, &jb, w - jb.wg_start, part, T.prec, scale_mode,
+                                 reinterpret_cast<unsigned char*>(ws), st, pool);
+      }
+      break;
+    }
+    default: {  // GEMM
+      const GemmProb* probs = prog.gemms + T.first;
+      for (int w = 0; w < T.total; w++) {
+        const GemmProb& P = probs[find_prob(probs, T.count, w)];
+        const int t = w - P.tile_start;
+        if (T.tile == 128) {
+          switch (T.prec) {
+            case F16: nb_gemm_q<_Float16, 128>(L, ldl, (const _Float16*)ws, &P, t, part, T.prec, scale_mode, st, pool); break;
+            case E4M3: nb_gemm_q<unsigned char, 128>(L, ldl, (const unsigned char*)ws, &P, t, part, T.prec, scale_mode, st, pool); break;
+            case F32: nb_gemm_d<float, 128>(L, ldl, &P, t, part, T.prec, scale_mode, st, pool); break;
+            default: nb_gemm_d<double, 128>(L, ldl, &P, t, part, T.prec, scale_mode, st, pool); break;
+          }
+        } else {
+          switch (T.prec) {
+            case F16: nb_gemm_q<_Float16, 64>(L, ldl, (const _Float16*)ws, &P, t, part, T.prec, scale_mode, st, pool); break;
+            case E4M3: nb_gemm_q<unsigned char, 64>(L, ldl, (const unsigned char*)ws, &P, t, part, T.prec, scale_mode, st, pool); break;
+            case F32: nb_gemm_d<float, 64>(L, ldl, &P, t, part, T.prec, scale_mode, st, pool); break;
+            default: nb_gemm_d<double, 64>(L, ldl, &P, t, part, T.prec, scale_mode, st, pool); break;
+          }
+        }
+      }
+      break;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
+  __shared__ __attribute__((aligned(16))) char pool[kPool];
+  __shared__ int qslot;
+  const int tid = threadIdx.x;
+  char* ws = prog.ws + (size_t)blockIdx.x * prog.ws_stride;
+  double* part = prog.part + (size_t)blockIdx.x * prog.part_stride;
+  double* scr = prog.scratch + (size_t)blockIdx.x * prog.scratch_stride;
+  DevStatus* st = prog.status + blockIdx.x;
+  for (;;) {
+    if (tid == 0) qslot = (int)atomicAdd(prog.queue, 1u);
+    __syncthreads();
+    const int q = qslot;
+    __syncthreads();
+    if (q >= prog.batch) break;            // every wave of the workgroup leaves here
+    const BatchMat M = prog.mats[prog.order[q]];
+    const int n = M.n;
+    double* L = M.L;
+    if (tid == 0) {
+      __hip_atomic_store(&st->failed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->nonfinite, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // L <- tril(A)
+    if (M.L != M.A)
+      for (int j = 0; j < n; j++)
+        for (int i = j + tid; i < n; i += 256) L[i + (int64_t)j * M.ldl] = M.A[i + (int64_t)j * M.lda];
+    __syncthreads();
+    for (int t = M.t0; t < M.t1; t++)
+      run_task(prog.tasks[t], prog, L, M.ldl, ws, part, st, prog.scale_mode, pool);
+    __threadfence_block();
+    __syncthreads();
+    // the bodies record failures with L2 atomics: read them past the L1
+    const unsigned long long fst = __hip_atomic_load(&st->failed, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int nfs = __hip_atomic_load(&st->nonfinite, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    int status = 0;
+    long long failed = 0;
+    if (fst != ~0ull) {
+      status = MPCHOL_NOT_SPD_CODE;
+      failed = (long long)fst;
+    } else if (nfs) {
+      status = MPCHOL_NONFINITE_CODE;
+    }
+    int iters = 0;
+    double corr = 0.0;
+    if (status == 0 && prog.nrhs > 0) {
+      double* R = scr;                       // n x nrhs
+      for (int c = 0; c < prog.nrhs; c++)
+        for (int i = tid; i < n; i += 256) M.X[i + (int64_t)c * n] = M.B[i + (int64_t)c * n];
+      __syncthreads();
+      wg_trsv(0, L, M.ldl, n, prog.nrhs, M.X, pool);
+      wg_trsv(1, L, M.ldl, n, prog.nrhs, M.X, pool);
+      if (prog.max_iter > 0) {
+        status = MPCHOL_NOT_CONVERGED_CODE;
+        double prev = __longlong_as_double(0x7FF0000000000000ll);
+        int grew = 0;
+        for (int it = 1; it <= prog.max_iter; it++) {
+          wg_residual(M.A, M.lda, n, prog.nrhs, M.X, M.B, n, R, pool);
+          wg_trsv(0, L, M.ldl, n, prog.nrhs, R, pool);
+          wg_trsv(1, L, M.ldl, n, prog.nrhs, R, pool);
+          const double w = wg_update(n, prog.nrhs, M.X, R, pool);
+          iters = it;
+          corr = w;
+          if (!(w <= 1.7976931348623157e308)) {
+            status = MPCHOL_NONFINITE_CODE;
+            break;
+          }
+          if (w <= prog.tol) {
+            status = 0;
+            break;
+          }
+          if (w > prev) {
+            if (++grew >= 2) break;
+          } else {
+            grew = 0;
+          }
+          prev = w;
+        }
+      }
+    }
+    if (tid == 0) {
+      BatchInfo& I = prog.info[prog.order[q]];
+      I.status = status;
+      I.ir_iters = iters;
+      I.failed_index = failed;
+      I.final_rel_corr = corr;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+__global__ void k_queue_reset(unsigned int* q) {
+  if (threadIdx.x == 0) *q = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_batched(const BatchProgram& prog, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, prog.queue);
+  hipLaunchKernelGGL(k_batched, dim3(nwg), dim3(256), 0, s, prog);
+  return hipGetLastError();
+}
+
+}  // namespace mpc

@@ -16,262 +16,22 @@
 // which equals the correctly rounded a / b (Markstein 1990) barring
 // overflow/underflow, with three dependent operations instead of a full
 // division on the elimination chain.
-#include "internal.h"
+#include "dev_leaf.h"
 
 namespace mpc {
 
-constexpr int KL = kKernelLeaf;   // 128
-constexpr int PW = 16;            // panel width
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct LeafMfma;
-template <> struct LeafMfma<double> {
-  typedef f64x4 acc_t;
-  static __device__ inline acc_t mma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // output row of lane l, register r (measured layout)
-  static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-template <> struct LeafMfma<float> {
-  typedef f32x4 acc_t;
-  static __device__ inline acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-
-__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
-
-// Value of v in lane `src` of the wave (uniform src).
-__device__ inline double lane_bcast(double v, int src) {
-  long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-  int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline float lane_bcast(float v, int src) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
-
-// a / b from y = RN(1 / b): correctly rounded quotient (Markstein).
-__device__ inline double qdiv(double a, double b, double y) {
-  double q0 = a * y;
-  double r = fma(-q0, b, a);
-  return fma(r, y, q0);
-}
-__device__ inline float qdiv(float a, float b, float y) {
-  float q0 = a * y;
-  float r = fmaf(-q0, b, a);
-  return fmaf(r, y, q0);
-}
-
-// ---------------------------------------------------------------- POTRF
-// A(i0:i0+m, i0:i0+m) <- chol, lower, m <= 128, whole block in LDS.  The block
-// is padded to mp = 16 ceil(m / 16) with an identity extension (pivots 1,
-// couplings 0), which leaves the leading m x m factor unchanged and makes the
-// panel code straight-line.  A pivot <= 0 / NaN records its 1-based global
-// column (atomic min) and the elimination continues with NaN.
 template <typename T>
 __global__ __launch_bounds__(256) void k_potrf_leaf(double* __restrict__ Lm, int64_t ldl,
                                                     int64_t i0, int m, DevStatus* st) {
-  constexpr int LD = KL + 1;
-  __shared__ T a[KL * LD];   // a[i * LD + j], row-major, lower part used
-  double* A = Lm + i0 + i0 * ldl;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mp = (m + PW - 1) / PW * PW;
-  // batched unconditional loads (addresses clamped into the block)
-  {
-    // all 64 loads of a thread in flight before the first LDS store
-    double v[KL * KL / 256];
-#pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      v[r] = A[min(i, m - 1) + (int64_t)min(j, m - 1) * ldl];
-    }
-#pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      if (i < mp && j < mp && i >= j) a[i * LD + j] = (i < m && j < m) ? (T)v[r] : (T)(i == j ? 1 : 0);
-    }
-  }
-  __syncthreads();
-  for (int p = 0; p < mp; p += PW) {
-    if (wave == 0) {
-      // panel elimination in registers: lane owns rows ra = lane and rb = lane + 64;
-      // the panel's own rows p..p+15 all live in the same half (PW divides 64)
-      const int ra = lane, rb = lane + 64;
-      const bool lo = p < 64;
-      T xa[PW], xb[PW];
-#pragma unroll
-      for (int c = 0; c < PW; c++) {
-        xa[c] = (ra >= p && ra < mp) ? a[ra * LD + p + c] : (T)0;
-        xb[c] = (rb >= p && rb < mp) ? a[rb * LD + p + c] : (T)0;
-      }
-#pragma unroll
-      for (int jj = 0; jj < PW; jj++) {
-        const int j = p + jj;
-        const T d = lane_bcast(lo ? xa[jj] : xb[jj], j & 63);
-        if (lane == 0 && j < m && (!(d > (T)0) || !isfinite((double)d)))
-          atomicMin(&st->failed, (unsigned long long)(i0 + j + 1));
-        const T ljj = sqrt(d);
-        const T qa = xa[jj] / ljj, qb = xb[jj] / ljj;
-        xa[jj] = ra == j ? ljj : (ra > j ? qa : xa[jj]);
-        xb[jj] = rb == j ? ljj : (rb > j ? qb : xb[jj]);
-        const T colv = lo ? xa[jj] : xb[jj];
-#pragma unroll
-        for (int kk = jj + 1; kk < PW; kk++) {
-          const int k = p + kk;
-          const T lkj = lane_bcast(colv, k & 63);
-          const T ta = xa[kk] - xa[jj] * lkj, tb = xb[kk] - xb[jj] * lkj;
-          xa[kk] = ra >= k ? ta : xa[kk];
-          xb[kk] = rb >= k ? tb : xb[kk];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < PW; c++) {
-        if (ra >= p + c && ra < mp) a[ra * LD + p + c] = xa[c];
-        if (rb >= p + c && rb < mp) a[rb * LD + p + c] = xb[c];
-      }
-    }
-    __syncthreads();
-    // trailing update: a[i][k] -= sum_{q in panel} a[i][q] a[k][q], p+16 <= k <= i < mp
-    const int r0 = p + PW;
-    const int nt = (mp - r0) / 16;
-    const int ntiles = nt * (nt + 1) / 2;
-    for (int t = wave; t < ntiles; t += 4) {
-      int tc = 0, rem = t;
-      while (rem >= nt - tc) { rem -= nt - tc; tc++; }
-      const int tr = tc + rem;
-      const int ib = r0 + tr * 16, kb = r0 + tc * 16;
-      typename LeafMfma<T>::acc_t acc;
-      for (int r = 0; r < 4; r++) acc[r] = 0;
-#pragma unroll
-      for (int q0 = 0; q0 < PW; q0 += 4) {
-        const int qq = q0 + (lane >> 4);
-        const T av = a[(ib + (lane & 15)) * LD + p + qq];
-        const T bv = a[(kb + (lane & 15)) * LD + p + qq];
-        acc = LeafMfma<T>::mma(av, bv, acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int i = ib + LeafMfma<T>::row(lane, r), k = kb + (lane & 15);
-        if (i >= k) a[i * LD + k] = a[i * LD + k] - acc[r];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll 16
-  for (int r = 0; r < KL * KL / 256; r++) {
-    const int idx = tid + 256 * r;
-    const int i = idx % KL, j = idx / KL;
-    if (i < m && j < m && i >= j) A[i + (int64_t)j * ldl] = (double)a[i * LD + j];
-  }
+  __shared__ __attribute__((aligned(16))) char pool[potrf_leaf_lds_bytes<T>()];
+  potrf_leaf_body<T>(Lm, ldl, i0, m, st, pool);
 }
 
-// ---------------------------------------------------------------- TRSM
-// B <- B L^{-T}: B = A(r0:r0+m, c0:c0+k), L = A(c0:c0+k, c0:c0+k), k <= 128.
-// Rows of B are independent; each workgroup solves 64 of them.  L is kept in
-// LDS packed by columns (lower part only), padded to kp = 16 ceil(k / 16) with
-// an identity extension (B's padding columns are zero), so the panel code is
-// straight-line.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm_leaf(double* __restrict__ Lm, int64_t ldl,
                                                    int64_t r0, int64_t m, int64_t c0, int k) {
-  constexpr int LDB = KL + 1;
-  __shared__ T l[KL * (KL + 1) / 2];
-  __shared__ T b[64 * LDB];          // b[r * LDB + c]
-  __shared__ T inv[KL];              // RN(1 / L(j, j))
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t rb = r0 + (int64_t)blockIdx.x * 64;
-  const int rows = (int)min((int64_t)64, r0 + m - rb);
-  const int kp = (k + PW - 1) / PW * PW;
-  const double* L = Lm + c0 + c0 * ldl;
-  double* B = Lm + rb + c0 * ldl;
-  auto loff = [kp](int i, int j) { return j * kp - (j * (j - 1)) / 2 + (i - j); };  // i >= j
-  {
-    // all loads of a thread in flight before the first LDS store
-    double v[KL * KL / 256], w[64 * KL / 256];
-#pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      v[r] = L[min(i, k - 1) + (int64_t)min(j, k - 1) * ldl];
-    }
-#pragma unroll
-    for (int r = 0; r < 64 * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx & 63, j = idx >> 6;
-      w[r] = B[min(i, rows - 1) + (int64_t)min(j, k - 1) * ldl];
-    }
-#pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      if (i < kp && j < kp && i >= j) l[loff(i, j)] = (i < k && j < k) ? (T)v[r] : (T)(i == j ? 1 : 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 64 * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx & 63, j = idx >> 6;
-      if (j < kp) b[i * LDB + j] = (i < rows && j < k) ? (T)w[r] : (T)0;
-    }
-  }
-  __syncthreads();
-  if (tid < kp) inv[tid] = (T)1 / l[loff(tid, tid)];
-  __syncthreads();
-  for (int p = 0; p < kp; p += PW) {
-    if (wave == 0) {
-      // substitution inside the panel, lane = row, in registers
-      T x[PW];
-#pragma unroll
-      for (int jj = 0; jj < PW; jj++) x[jj] = b[lane * LDB + p + jj];
-#pragma unroll
-      for (int jj = 0; jj < PW; jj++) {
-        const int j = p + jj;
-        const int cb = loff(j, j);          // column j starts at its diagonal
-        x[jj] = qdiv(x[jj], l[cb], inv[j]);
-#pragma unroll
-        for (int qq = jj + 1; qq < PW; qq++) x[qq] = x[qq] - x[jj] * l[cb + (qq - jj)];
-      }
-#pragma unroll
-      for (int jj = 0; jj < PW; jj++) b[lane * LDB + p + jj] = x[jj];
-    }
-    __syncthreads();
-    // b[:, q] -= b[:, panel] L[q, panel]^T for q >= p + 16 (tiles of 16 rows x 16 cols)
-    const int q0c = p + PW;
-    const int ncol = (kp - q0c) / 16;
-    const int ntiles = 4 * ncol;
-    for (int t = wave; t < ntiles; t += 4) {
-      const int rt = t & 3, ct = t >> 2;
-      const int rbase = rt * 16, cbase = q0c + ct * 16;
-      typename LeafMfma<T>::acc_t acc;
-      for (int r = 0; r < 4; r++) acc[r] = 0;
-#pragma unroll
-      for (int s0 = 0; s0 < PW; s0 += 4) {
-        const int s = s0 + (lane >> 4);
-        const T av = b[(rbase + (lane & 15)) * LDB + p + s];      // A(row, s)
-        const T bv = l[loff(cbase + (lane & 15), p + s)];         // B(s, col) = L(col, p+s)
-        acc = LeafMfma<T>::mma(av, bv, acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = rbase + LeafMfma<T>::row(lane, r), col = cbase + (lane & 15);
-        b[row * LDB + col] = b[row * LDB + col] - acc[r];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll 16
-  for (int r = 0; r < 64 * KL / 256; r++) {
-    const int idx = tid + 256 * r;
-    const int i = idx & 63, j = idx >> 6;
-    if (j < k && i < rows) B[i + (int64_t)j * ldl] = (double)b[i * LDB + j];
-  }
+  __shared__ __attribute__((aligned(16))) char pool[trsm_leaf_lds_bytes<T>()];
+  trsm_leaf_rows<T>(Lm, ldl, r0, m, c0, k, blockIdx.x, pool);
 }
 
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m, DevStatus* st,

@@ -70,6 +70,7 @@ struct Builder {
   Plan& P;
   const mpchol_tree& t;
   int64_t ldl;
+  bool single_wg = false;
   int64_t next_node = 0;
   size_t ws_cursor = 0;   // bytes used by the current group of quantized copies
   int64_t part_cursor = 0;
@@ -220,7 +221,13 @@ struct Builder {
         int64_t tm = cdiv(g.m, 128);
         t128 += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, 128);
       }
-      L.tile = t128 >= 256 ? 128 : 64;
+      if (single_wg) {
+        int mn = 1 << 30;
+        for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
+        L.tile = mn >= 128 ? 128 : 64;
+      } else {
+        L.tile = t128 >= 256 ? 128 : 64;
+      }
       int tiles = 0;
       for (auto& g : gp) {
         g.tiles_m = (int)cdiv(g.m, L.tile);
@@ -341,13 +348,14 @@ struct Builder {
 
 }  // namespace
 
-void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t) {
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg) {
   P.n = n;
   P.ldl = ldl;
   P.tree = *t;
   P.node_prec.assign(t->node_prec, t->node_prec + t->n_nodes);
   P.tree.node_prec = nullptr;
   Builder B(P, P.tree, ldl);
+  B.single_wg = single_wg;
   B.potrf(0, n, 0);
   P.stats.n_launch = (int64_t)P.launches.size();
 }

@@ -46,7 +46,9 @@ struct Plan {
 // Validates the descriptor; returns 0 or a negative/positive mpchol code.
 int validate_tree(const mpchol_tree* t);
 std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t);
-void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t);
+// single_wg: the plan runs inside one workgroup (batched executor); GEMM
+// tiles are chosen for per-workgroup efficiency instead of chip occupancy.
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg = false);
 int64_t split_rule(int64_t m, int32_t align);
 
 }  // namespace mpc

@@ -23,7 +23,8 @@ import numpy as np
 
 E4M3, F16, F32, F64 = 0, 1, 2, 3
 OK, NOT_SPD, NONFINITE, NOT_CONVERGED, HIP_ERROR, NOT_SUPPORTED = 0, 1, 2, 3, 4, 5
-PROF_KINDS = ["gemm_e4m3", "gemm_f16", "gemm_f32", "gemm_f64", "cast", "maxabs", "potrf", "trsm"]
+PROF_KINDS = ["gemm_e4m3", "gemm_f16", "gemm_f32", "gemm_f64", "cast", "maxabs", "potrf", "trsm",
+              "trsv", "residual"]
 ABI_VERSION = 1
 MAX_LEVELS = 24
 
@@ -86,6 +87,7 @@ def _load() -> ct.CDLL:
                                       ct.POINTER(i64)]
     lib.mpchol_quantize.argtypes = [vp, i64, i64, vp, i64, i32, i32, vp, i64,
                                     ct.POINTER(dbl), vp]
+    lib.mpchol_set_tune_table.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32)]
     lib.mpchol_profile.argtypes = [vp, ct.c_uint32]
     lib.mpchol_profile_read.argtypes = [vp, ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(i64)]
     lib.mpchol_version.restype = ct.c_char_p
@@ -273,24 +275,38 @@ class Context:
             raise RuntimeError("mpchol_profile_read failed")
         return {k: (ms[i], wk[i], nl[i]) for i, k in enumerate(PROF_KINDS)}
 
-    def factor_batched(self, A_list, L_list, B_list, X_list, ns, tree: Tree, nrhs: int,
+    def set_tune_table(self, nmax: Sequence[int], leaf: Sequence[int]):
+        """Leaf size by system size for factor_batched (autotuner output)."""
+        k = len(nmax)
+        a = (ct.c_int32 * max(k, 1))(*nmax)
+        b = (ct.c_int32 * max(k, 1))(*leaf)
+        r = lib.mpchol_set_tune_table(self._h, k, a, b)
+        if r != 0:
+            raise ValueError(f"mpchol_set_tune_table: invalid argument {-r}")
+
+    def factor_batched(self, A_list, L_list, ns, tree: Tree, B_list=None, X_list=None,
                        tol: float = 1e-13, max_iter: int = 20, stream=None):
-        """Factor + refined solve of independent systems; returns list of info dicts."""
+        """Factor (+ solve and refine when B_list/X_list are given) independent
+        systems in one persistent launch; returns (worst status, info dicts).
+        B_i / X_i: tensors of shape (nrhs, n_i) (column-major n_i x nrhs)."""
         batch = len(A_list)
+        nrhs = B_list[0].shape[0] if B_list else 0
         n_arr = (ct.c_int64 * batch)(*ns)
         lda = (ct.c_int64 * batch)(*[a.shape[1] for a in A_list])
         ldl = (ct.c_int64 * batch)(*[l.shape[1] for l in L_list])
         Ap = (ct.c_void_p * batch)(*[a.data_ptr() for a in A_list])
         Lp = (ct.c_void_p * batch)(*[l.data_ptr() for l in L_list])
-        Bp = (ct.c_void_p * batch)(*[b.data_ptr() for b in B_list])
-        Xp = (ct.c_void_p * batch)(*[x.data_ptr() for x in X_list])
+        Bp = (ct.c_void_p * batch)(*[b.data_ptr() for b in B_list]) if B_list else None
+        Xp = (ct.c_void_p * batch)(*[x.data_ptr() for x in X_list]) if X_list else None
         infos = (CInfo * batch)()
         t, keep = tree.to_c()
         r = lib.mpchol_factor_batched(self._h, batch, n_arr, Ap, lda, Lp, ldl, nrhs, Bp, Xp, tol,
                                       max_iter, ct.byref(t), _stream_handle(stream), infos)
         if r < 0:
             raise ValueError(f"mpchol_factor_batched: invalid argument {-r}")
-        return [infos[i].as_dict() for i in range(batch)]
+        if r == HIP_ERROR:
+            raise RuntimeError("mpchol_factor_batched: HIP error")
+        return r, [infos[i].as_dict() for i in range(batch)]
 
 
 def version() -> str:
