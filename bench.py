@@ -108,8 +108,93 @@ def cpu_baseline(n_full: int, ratio: float, offdiag, leaf: int, budget_s: float)
                       f"{t:.1f} s on {_cpu_model()}"}
 
 
+def bench_batched(args) -> dict:
+    """4096 systems, sizes log-uniform in [64, 2048], dominance ratios uniform
+    in [1.05, 4], 4 right-hand sides each, all-FP16 off-diagonal tree with FP64
+    leaves and split alignment 32, leaf/tile per size from the tune table:
+    one persistent launch per step factors, solves and refines all of them."""
+    import numpy as np
+    import torch
+
+    from paper_2601_08082_amd import mpchol as M
+    from paper_2601_08082_amd import spdgen
+    from paper_2601_08082_amd.workloads import DeviceBatch, batch_recipe
+
+    ns, ratios, seeds = batch_recipe(args.batch, 64, 2048, 1.05, 4.0, seed=4)
+    db = DeviceBatch(ns, ratios, seeds, 4)
+    ctx = M.Context(0)
+    tune = os.path.join(ROOT, "paper_2601_08082_amd", "tune_mi355x.json")
+    tuned = os.path.exists(tune)
+    if tuned:
+        ctx.load_tune_table(tune)
+    tree = M.Tree(leaf=64, offdiag=[M.F16], leaf_prec=M.F64, split_align=32)
+    flops = db.flops()
+
+    def step():
+        st, infos = ctx.factor_batched(db.A, db.L, db.ns, tree, db.B, db.X, tol=1e-13, max_iter=20)
+        return st, infos
+
+    for _ in range(args.warmup):
+        step()
+    ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, infos = step()
+        ms.append(infos[0]["ms_factor"])
+        if st != 0:
+            bad = [i for i, x in enumerate(infos) if x["status"] != 0]
+            raise RuntimeError(f"batched step: {len(bad)} systems failed, first {infos[bad[0]]}")
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kern_ms = float(np.median(ms))
+    iters = np.array([x["ir_iters"] for x in infos])
+
+    # one more step with the task classes timed inside the kernel (outside the timed region)
+    ctx.profile(M.PROF_KINDS)
+    step()
+    breakdown = {k: {"wg_ms": v[0], "tasks": v[2]} for k, v in ctx.profile_read().items() if v[2]}
+    ctx.profile([])
+
+    # Gershgorin certificate on a sample of systems (FP64 residual on the CPU)
+    worst = 0.0
+    for i in list(range(0, len(ns), max(1, len(ns) // 32))):
+        n = ns[i]
+        Ah = M.from_device_cm(db.A[i])
+        x = M.from_device_cm(db.X[i])[:n]
+        b = M.from_device_cm(db.B[i])[:n]
+        lam = spdgen.gershgorin_lower_bound(n, ratios[i], 0.0, Ah)
+        r = b - Ah @ x
+        worst = max(worst, float(np.max(np.linalg.norm(r, axis=0) / lam / np.linalg.norm(x, axis=0))))
+    ctx.close()
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    return {
+        "metric": "effective TFLOP/s (sum n^3/3) of batched factor + refined solve",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 MFMA (f32 acc) + f64 leaves, f64 in/out", "data": "synthetic",
+        "config": {"workload": f"{len(ns)} SPD systems, n log-uniform [64, 2048], ratio U[1.05, 4], "
+                               f"4 rhs, tree [F16] leaf FP64 split_align 32, "
+                               f"{'tuned' if tuned else 'untuned (leaf 64)'} per-size leaf/tile",
+                   "batch": len(ns), "total_flops": flops, "nrhs": 4,
+                   "parallelism": "single GPU, one persistent launch"},
+        "ir_iters_max": int(iters.max()), "ir_iters_mean": float(iters.mean()),
+        "solution_error_certificate_sample": worst,
+        "task_breakdown_workgroup_ms": breakdown,
+        "roofline": {"bound": "mfma", "kernel": "k_batched (persistent, whole path)",
+                     "achieved": achieved, "peak": PEAKS["gemm_f16"][0], "unit": "TFLOP/s",
+                     "frac": achieved / PEAKS["gemm_f16"][0], "traffic": None,
+                     "ms_per_launch": kern_ms},
+        "cpu_baseline": None,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -123,6 +208,10 @@ def main() -> int:
         print("bench.py runs on one GPU only: the single-matrix path is not sharded "
               "across GPUs in this build (see the design notes on sharding)", file=sys.stderr)
         return 2
+
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return 0
 
     import numpy as np
     import torch

@@ -157,8 +157,9 @@ int mpchol_solve(mpchol_ctx ctx, int64_t n, int64_t nrhs, const double* A, int64
  *   nrhs        right-hand sides per system, 0..16 (B_i, X_i are n_i x nrhs,
  *               leading dimension n_i); 0: factor only.
  *   tol, max_iter  the refinement rule of mpchol_solve, per system.
- *   tree        descriptor shared by all systems; its leaf is replaced per
- *               system by the context's tune table (mpchol_set_tune_table).
+ *   tree        descriptor shared by all systems; its leaf, split alignment
+ *               and GEMM tile are replaced per system by the context's tune
+ *               table (mpchol_set_tune_table).
  *   info_host   NULL or host array of batch mpchol_info (status, failed
  *               index, refinement steps, last correction; ms_factor = the
  *               whole launch).
@@ -222,19 +223,32 @@ enum {
  * on the launch's own stream.  mpchol_profile_read waits for the recorded
  * events and returns, per class, the summed device milliseconds, the summed
  * algorithmic work (flops for GEMM/POTRF/TRSM, bytes for cast/max-abs) and the
- * number of launches.  Arrays have MPCHOL_PROF_KINDS entries (NULL: skip). */
+ * number of launches.  Arrays have MPCHOL_PROF_KINDS entries (NULL: skip).
+ * In mpchol_factor_batched the classes are timed inside the persistent
+ * kernel instead: ms is the wall-clock time of each task class summed over
+ * the workgroups (workgroup-milliseconds), launches counts the tasks, and
+ * work is not accumulated. */
 int mpchol_profile(mpchol_ctx ctx, uint32_t kind_mask);
 int mpchol_profile_read(mpchol_ctx ctx, double* ms, double* work, int64_t* launches);
 
 /*
- * Leaf size by system size for mpchol_factor_batched (the autotuner's
- * output): a system of order n uses leaf[i] for the first i with
- * n <= nmax[i] (nmax strictly increasing), the descriptor's leaf above the
- * last entry.  count 0 clears the table.  Copies the arrays.
- * Errors: -2 count < 0; -3 nmax NULL or not increasing; -4 a leaf < 1.
+ * Per-size plan choices for mpchol_factor_batched (the autotuner's output).
+ * A system of order n uses the first entry with n <= nmax (nmax strictly
+ * increasing over the table); above the last entry the descriptor applies.
  */
-int mpchol_set_tune_table(mpchol_ctx ctx, int32_t count, const int32_t* nmax,
-                          const int32_t* leaf);
+typedef struct {
+  int32_t nmax;         /* entry covers orders n <= nmax */
+  int32_t leaf;         /* leaf size b >= 1 */
+  int32_t split_align;  /* 0: the descriptor's; else >= 1 (split rule of the descriptor) */
+  int32_t tile;         /* 0: automatic; 64 or 128: GEMM output tile */
+} mpchol_tune_entry;
+
+/*
+ * Install the tune table of a context (copied; count 0 clears it).
+ * Errors: -2 count < 0; -3 table NULL or nmax not increasing; -4 a leaf < 1;
+ * -5 split_align < 0; -6 tile not 0, 64 or 128.
+ */
+int mpchol_set_tune_table(mpchol_ctx ctx, int32_t count, const mpchol_tune_entry* table);
 
 /* Human-readable build/version string (static storage). */
 const char* mpchol_version(void);

@@ -47,6 +47,7 @@ struct BatchProgram {
   double* scratch;          // per-workgroup residual / correction (n x nrhs)
   size_t scratch_stride;
   DevStatus* status;        // per-workgroup status words
+  unsigned long long* prof; // NULL, or per task class [wall-clock ticks, tasks] summed over workgroups
   int32_t batch, nrhs, max_iter, scale_mode;
   double tol;
 };

@@ -54,7 +54,7 @@ struct mpchol_ctx_s {
   double acc_work[MPCHOL_PROF_KINDS] = {0};
   int64_t acc_n[MPCHOL_PROF_KINDS] = {0};
   // leaf choice by size for the batched path (mpchol_set_tune_table)
-  std::vector<int32_t> tune_nmax, tune_leaf;
+  std::vector<mpchol_tune_entry> tune;   // per-size plan choices of the batched path
   // batched program cache: device arrays and the captured graph of the last call
   struct Batch {
     std::string key;
@@ -258,10 +258,11 @@ static int status_from(const DevStatus& h, mpchol_info* info) {
   return st;
 }
 
-static int32_t tuned_leaf(mpchol_ctx c, int64_t n, int32_t dflt) {
-  for (size_t i = 0; i < c->tune_nmax.size(); i++)
-    if (n <= c->tune_nmax[i]) return c->tune_leaf[i];
-  return dflt;
+// the tune-table entry for a system of order n (NULL: the descriptor applies)
+static const mpchol_tune_entry* tuned(mpchol_ctx c, int64_t n) {
+  for (const mpchol_tune_entry& e : c->tune)
+    if (n <= e.nmax) return &e;
+  return nullptr;
 }
 
 template <typename T>
@@ -470,17 +471,17 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
   return status;
 }
 
-int mpchol_set_tune_table(mpchol_ctx c, int32_t count, const int32_t* nmax,
-                          const int32_t* leaf) {
+int mpchol_set_tune_table(mpchol_ctx c, int32_t count, const mpchol_tune_entry* table) {
   if (!c) return -1;
   if (count < 0) return -2;
-  if (count > 0 && (!nmax || !leaf)) return -3;
+  if (count > 0 && !table) return -3;
   for (int32_t i = 0; i < count; i++) {
-    if (leaf[i] < 1) return -4;
-    if (i > 0 && nmax[i] <= nmax[i - 1]) return -3;
+    if (i > 0 && table[i].nmax <= table[i - 1].nmax) return -3;
+    if (table[i].leaf < 1) return -4;
+    if (table[i].split_align < 0) return -5;
+    if (table[i].tile != 0 && table[i].tile != 64 && table[i].tile != 128) return -6;
   }
-  c->tune_nmax.assign(nmax, nmax + count);
-  c->tune_leaf.assign(leaf, leaf + count);
+  c->tune.assign(table, table + count);
   return 0;
 }
 
@@ -519,8 +520,11 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
 
   // cache key: everything the device program depends on
   std::ostringstream key;
-  key << batch << '|' << nrhs << '|' << tol << '|' << max_iter << '|' << plan_key(0, 1, tree);
-  for (size_t i = 0; i < c->tune_nmax.size(); i++) key << c->tune_nmax[i] << ':' << c->tune_leaf[i] << ',';
+  const bool bprof = c->prof_mask != 0;
+  key << batch << '|' << nrhs << '|' << tol << '|' << max_iter << '|' << bprof << '|'
+      << plan_key(0, 1, tree);
+  for (const mpchol_tune_entry& e : c->tune)
+    key << e.nmax << ':' << e.leaf << ':' << e.split_align << ':' << e.tile << ',';
   for (int64_t i = 0; i < batch; i++) {
     key << '|' << n_host[i] << ',' << lda_host[i] << ',' << ldl_host[i] << ',' << (const void*)A_dev[i]
         << ',' << (const void*)L_dev[i];
@@ -539,12 +543,17 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
     int64_t parts_max = 1;
     for (int64_t i = 0; i < batch; i++) {
       mpchol_tree t = *tree;
-      t.leaf = tuned_leaf(c, n_host[i], tree->leaf);
-      std::string pk = plan_key(n_host[i], ldl_host[i], &t);
+      int tile = 0;
+      if (const mpchol_tune_entry* e = tuned(c, n_host[i])) {
+        t.leaf = e->leaf;
+        if (e->split_align > 0) t.split_align = e->split_align;
+        tile = e->tile;
+      }
+      std::string pk = plan_key(n_host[i], ldl_host[i], &t) + "/t" + std::to_string(tile);
       auto it = seen.find(pk);
       if (it == seen.end()) {
         Plan P;
-        build_plan(P, n_host[i], ldl_host[i], &t, true);
+        build_plan(P, n_host[i], ldl_host[i], &t, true, tile);
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
           BatchTask T{};
@@ -626,6 +635,11 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
     HIPCHK(hipMalloc(&p, sizeof(DevStatus) * (size_t)nwg));
     BT.bufs.push_back(p);
     G.status = (DevStatus*)p;
+    if (bprof) {
+      HIPCHK(hipMalloc(&p, sizeof(unsigned long long) * 2 * MPCHOL_PROF_KINDS));
+      BT.bufs.push_back(p);
+      G.prof = (unsigned long long*)p;
+    }
     G.batch = (int32_t)batch;
     G.nrhs = (int32_t)nrhs;
     G.max_iter = max_iter;
@@ -655,6 +669,19 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (BT.prog.prof) {
+    // per task class: workgroup-milliseconds (wall clock summed over workgroups) and task counts
+    unsigned long long h[2 * MPCHOL_PROF_KINDS];
+    int khz = 0;
+    HIPCHK(hipMemcpy(h, BT.prog.prof, sizeof(h), hipMemcpyDeviceToHost));
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+    for (int k = 0; k < MPCHOL_PROF_KINDS; k++) {
+      if (c->prof_mask & (1u << k)) {
+        c->acc_ms[k] += khz > 0 ? (double)h[2 * k] / (double)khz : 0.0;
+        c->acc_n[k] += (int64_t)h[2 * k + 1];
+      }
+    }
+  }
   int worst = 0;
   for (int64_t i = 0; i < batch; i++) {
     const BatchInfo& I = BT.hinfo[i];

@@ -58,122 +58,165 @@ __device__ inline void stage_block(double (*blk)[65], const double* __restrict__
   }
 }
 
-// X <- L^-1 X (trans 0) or L^-T X (trans 1), n x nrhs (ld n), one workgroup,
-// 64-row blocks.  pool: blk, dg [64][65] + acc[4][64][16] doubles.
-__device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, int64_t ldl, int n, int nrhs,
-                        double* X, char* pool) {
+// X <- L^-1 X (trans 0) or L^-T X (trans 1), n x nrhs (ld n, nrhs <= NR),
+// one workgroup, 64-row blocks.  Off-diagonal blocks: forward, lanes run
+// along the block's rows straight from memory (coalesced); transposed, the
+// block is staged through LDS.  The diagonal block is solved by wave 0 with
+// one lane per row.  LDS: blk, dg [64][65], xs [64][NR], acc [4][64][NR].
+template <int NR>
+__device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, int64_t ldl, int n,
+                                     int nrhs, double* X, char* pool) {
   typedef double Col[65];
-  Col* blk = reinterpret_cast<Col*>(pool);                             // blk[col][row]
-  Col* dg = blk + 64;                                                  // dg[col][row]
-  double* acc = reinterpret_cast<double*>(pool + 2 * 64 * 65 * 8);     // [4][64][16]
+  Col* blk = reinterpret_cast<Col*>(pool);
+  Col* dg = blk + 64;
+  double* xs = reinterpret_cast<double*>(pool + 2 * 64 * 65 * 8);   // [64][NR]
+  double* acc = xs + 64 * NR;                                        // [4][64][NR]
   const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int nb = (n + 63) / 64;
   for (int s = 0; s < nb; s++) {
     const int J = trans ? nb - 1 - s : s;
     const int j0 = J * 64, nj = min(64, n - j0);
-    double part[16];
-    for (int c = 0; c < 16; c++) part[c] = 0.0;
+    double part[NR];
+#pragma unroll
+    for (int c = 0; c < NR; c++) part[c] = 0.0;
     for (int u = 0; u < s; u++) {
       const int K = trans ? nb - 1 - u : u;
       const int k0 = K * 64, nk = min(64, n - k0);
       __syncthreads();
-      if (!trans) stage_block(blk, L, ldl, j0, k0, nj, nk);   // L(J, K)
-      else stage_block(blk, L, ldl, k0, j0, nk, nj);          // L(K, J)
+      for (int idx = tid; idx < 64 * NR; idx += 256) {
+        const int q = idx & 63, c = idx >> 6;
+        xs[q * NR + c] = (q < nk && c < nrhs) ? X[(k0 + q) + (int64_t)c * n] : 0.0;
+      }
+      if (trans) stage_block(blk, L, ldl, k0, j0, nk, nj);   // L(K, J)
       __syncthreads();
       if (!trans) {
-        for (int q = g; q < nk; q += 4) {
-          const double l = blk[q][r];
-          for (int c = 0; c < nrhs; c++) part[c] += l * X[(k0 + q) + (int64_t)c * n];
-        }
+        if (r < nj)
+          for (int q = g; q < nk; q += 4) {
+            const double l = L[(j0 + r) + (int64_t)(k0 + q) * ldl];
+#pragma unroll
+            for (int c = 0; c < NR; c++) part[c] += l * xs[q * NR + c];
+          }
       } else {
         for (int i = g; i < nk; i += 4) {
           const double l = blk[r][i];
-          for (int c = 0; c < nrhs; c++) part[c] += l * X[(k0 + i) + (int64_t)c * n];
+#pragma unroll
+          for (int c = 0; c < NR; c++) part[c] += l * xs[i * NR + c];
         }
       }
     }
     __syncthreads();
-    for (int c = 0; c < nrhs; c++) acc[(g * 64 + r) * 16 + c] = part[c];
+#pragma unroll
+    for (int c = 0; c < NR; c++) acc[(g * 64 + r) * NR + c] = part[c];
     stage_block(dg, L, ldl, j0, j0, nj, nj);
     __syncthreads();
     if (tid < 64) {
       const int i = tid;
-      double v[16];
-      for (int c = 0; c < 16; c++) {
-        double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * n] : 0.0;
-        v[c] = c < nrhs ? b - ((acc[(0 * 64 + i) * 16 + c] + acc[(1 * 64 + i) * 16 + c]) +
-                               (acc[(2 * 64 + i) * 16 + c] + acc[(3 * 64 + i) * 16 + c]))
-                        : 0.0;
+      double v[NR];
+#pragma unroll
+      for (int c = 0; c < NR; c++) {
+        const double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * n] : 0.0;
+        v[c] = b - ((acc[(0 * 64 + i) * NR + c] + acc[(1 * 64 + i) * NR + c]) +
+                    (acc[(2 * 64 + i) * NR + c] + acc[(3 * 64 + i) * NR + c]));
       }
       const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;
       for (int jj = 0; jj < nj; jj++) {
         const int j = trans ? nj - 1 - jj : jj;
         const double lij = trans ? dg[i][j] : dg[j][i];   // L(j, i) resp. L(i, j)
         const double ij = wg_bcast(inv, j);
-        for (int c = 0; c < nrhs; c++) {
+        const bool below = trans ? (i < j) : (i > j);
+#pragma unroll
+        for (int c = 0; c < NR; c++) {
           const double xj = wg_bcast(v[c], j) * ij;
           const double upd = v[c] - lij * xj;
-          const bool below = trans ? (i < j) : (i > j);
           v[c] = i == j ? xj : (below ? upd : v[c]);
         }
       }
-      for (int c = 0; c < nrhs; c++)
-        if (i < nj) X[(j0 + i) + (int64_t)c * n] = v[c];
+#pragma unroll
+      for (int c = 0; c < NR; c++)
+        if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * n] = v[c];
     }
     __syncthreads();
   }
 }
 
-// R = B - A X (A symmetric, lower stored), one workgroup, 64 x 64 blocks
-// staged through LDS.
+// R = B - A X (A symmetric, lower stored, read once), n x nrhs (nrhs <= NR),
+// one workgroup.  Each stored 64 x 64 block A(J, I), J >= I, is staged
+// through LDS and used twice: A(J, I) x_I into rows J (lane = row) and
+// A(J, I)^T x_J into rows I (lane = column); R holds the running sums of A X.
+// LDS: blk [64][65], xi, xj [64][NR].
+template <int NR>
 __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t lda, int n, int nrhs,
-                            const double* X, const double* B, int64_t ldb, double* R,
-                            char* pool) {
+                                         const double* X, const double* B, int64_t ldb, double* R,
+                                         char* pool) {
   typedef double Col[65];
-  Col* blk = reinterpret_cast<Col*>(pool);                          // blk[q][r] = A_sym(i0 + r, j0 + q)
-  double* acc = reinterpret_cast<double*>(pool + 64 * 65 * 8);     // [4][64][16]
-  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+  Col* blk = reinterpret_cast<Col*>(pool);                 // blk[q][r] = A(j0 + r, i0 + q)
+  double* xi = reinterpret_cast<double*>(pool + 64 * 65 * 8);
+  double* xj = xi + 64 * NR;
+  const int tid = threadIdx.x;
   const int nb = (n + 63) / 64;
+  for (int idx = tid; idx < n * nrhs; idx += 256) R[idx] = 0.0;
   for (int I = 0; I < nb; I++) {
     const int i0 = I * 64, ni = min(64, n - i0);
-    double part[16];
-    for (int c = 0; c < 16; c++) part[c] = 0.0;
-    for (int J = 0; J < nb; J++) {
+    __syncthreads();
+    for (int idx = tid; idx < 64 * NR; idx += 256) {
+      const int q = idx & 63, c = idx >> 6;
+      xi[q * NR + c] = (q < ni && c < nrhs) ? X[(i0 + q) + (int64_t)c * n] : 0.0;
+    }
+    double colsum[NR];                   // rows I (lane q = tid, wave 0), from the blocks below
+#pragma unroll
+    for (int c = 0; c < NR; c++) colsum[c] = 0.0;
+    for (int J = I; J < nb; J++) {
       const int j0 = J * 64, nj = min(64, n - j0);
       __syncthreads();
-      if (J < I) {
-        stage_block(blk, A, lda, i0, j0, ni, nj);
-      } else if (J > I) {
-        for (int idx = tid; idx < 64 * 64; idx += 256) {   // A(j0 + q, i0 + r), lanes along q
-          const int q = idx & 63, rr = idx >> 6;
-          blk[q][rr] = (rr < ni && q < nj) ? A[(j0 + q) + (int64_t)(i0 + rr) * lda] : 0.0;
-        }
-      } else {
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
-          const int i = idx & 63, q = idx >> 6;
-          double v = 0.0;
-          if (i < ni && q < nj)
-            v = i >= q ? A[(i0 + i) + (int64_t)(j0 + q) * lda] : A[(j0 + q) + (int64_t)(i0 + i) * lda];
-          blk[q][i] = v;
-        }
+      for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int rr = idx & 63, q = idx >> 6;
+        double v = 0.0;
+        if (rr < nj && q < ni && (J > I || rr >= q)) v = A[(j0 + rr) + (int64_t)(i0 + q) * lda];
+        blk[q][rr] = v;
+      }
+      for (int idx = tid; idx < 64 * NR; idx += 256) {
+        const int q = idx & 63, c = idx >> 6;
+        xj[q * NR + c] = (q < nj && c < nrhs) ? X[(j0 + q) + (int64_t)c * n] : 0.0;
       }
       __syncthreads();
-      for (int q = g; q < nj; q += 4) {
-        const double a = blk[q][r];
-        for (int c = 0; c < nrhs; c++) part[c] += a * X[(j0 + q) + (int64_t)c * n];
+      if (tid < 64) {
+        // rows of J: sum over q of A(j0 + r, i0 + q) x_I(q)  (diagonal block: q <= r)
+        const int rr = tid;
+        double y[NR];
+#pragma unroll
+        for (int c = 0; c < NR; c++) y[c] = 0.0;
+        for (int q = 0; q < 64; q++) {
+          const double a = blk[q][rr];
+#pragma unroll
+          for (int c = 0; c < NR; c++) y[c] += a * xi[q * NR + c];
+        }
+        if (rr < nj)
+#pragma unroll
+          for (int c = 0; c < NR; c++)
+            if (c < nrhs) R[(j0 + rr) + (int64_t)c * n] += y[c];
+      } else if (tid < 128) {
+        // rows of I: sum over r of A(j0 + r, i0 + q) x_J(r), strictly below the diagonal
+        const int q = tid - 64;
+        for (int rr = 0; rr < 64; rr++) {
+          const double a = (J > I || rr > q) ? blk[q][rr] : 0.0;
+#pragma unroll
+          for (int c = 0; c < NR; c++) colsum[c] += a * xj[rr * NR + c];
+        }
       }
     }
     __syncthreads();
-    for (int c = 0; c < nrhs; c++) acc[(g * 64 + r) * 16 + c] = part[c];
-    __syncthreads();
-    for (int idx = tid; idx < 64 * nrhs; idx += 256) {
-      const int ii = idx & 63, c = idx >> 6;
-      if (ii < ni) {
-        const double t = (acc[(0 * 64 + ii) * 16 + c] + acc[(1 * 64 + ii) * 16 + c]) +
-                         (acc[(2 * 64 + ii) * 16 + c] + acc[(3 * 64 + ii) * 16 + c]);
-        R[(i0 + ii) + (int64_t)c * n] = B[(i0 + ii) + (int64_t)c * ldb] - t;
-      }
+    if (tid >= 64 && tid < 128) {
+      const int q = tid - 64;
+      if (q < ni)
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+          if (c < nrhs) R[(i0 + q) + (int64_t)c * n] += colsum[c];
     }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * nrhs; idx += 256) {
+    const int i = idx % n, c = idx / n;
+    R[idx] = B[i + (int64_t)c * ldb] - R[idx];
   }
   __syncthreads();
 }
@@ -211,6 +254,25 @@ __device__ double wg_update(int n, int nrhs, double* X, const double* D, char* p
     __syncthreads();
   }
   return worst;
+}
+
+// X <- L^-T L^-1 X and R = B - A X with the register width for nrhs
+__device__ inline void wg_solve(const double* L, int64_t ldl, int n, int nrhs, double* X, char* pool) {
+  for (int t = 0; t < 2; t++) {
+    if (nrhs <= 1) wg_trsv<1>(t, L, ldl, n, nrhs, X, pool);
+    else if (nrhs <= 2) wg_trsv<2>(t, L, ldl, n, nrhs, X, pool);
+    else if (nrhs <= 4) wg_trsv<4>(t, L, ldl, n, nrhs, X, pool);
+    else if (nrhs <= 8) wg_trsv<8>(t, L, ldl, n, nrhs, X, pool);
+    else wg_trsv<16>(t, L, ldl, n, nrhs, X, pool);
+  }
+}
+__device__ inline void wg_resid(const double* A, int64_t lda, int n, int nrhs, const double* X,
+                                const double* B, int64_t ldb, double* R, char* pool) {
+  if (nrhs <= 1) wg_residual<1>(A, lda, n, nrhs, X, B, ldb, R, pool);
+  else if (nrhs <= 2) wg_residual<2>(A, lda, n, nrhs, X, B, ldb, R, pool);
+  else if (nrhs <= 4) wg_residual<4>(A, lda, n, nrhs, X, B, ldb, R, pool);
+  else if (nrhs <= 8) wg_residual<8>(A, lda, n, nrhs, X, B, ldb, R, pool);
+  else wg_residual<16>(A, lda, n, nrhs, X, B, ldb, R, pool);
 }
 
 // Non-inlined entry points: each body keeps its own register allocation
@@ -311,6 +373,24 @@ __device__ void run_task(const BatchTask& T, const BatchProgram& prog, double* L
   __syncthreads();
 }
 
+// profiling class of a task (the public per-launch-class numbering)
+__device__ inline int task_class(const BatchTask& T) {
+  switch (T.kind) {
+    case BatchTask::POTRF: return 6;
+    case BatchTask::TRSM: return 7;
+    case BatchTask::MAXABS: return 5;
+    case BatchTask::CAST: return 4;
+    default: return T.prec;   // GEMM by operand precision 0..3
+  }
+}
+
+__device__ inline void prof_add(unsigned long long* prof, int cls, unsigned long long t0) {
+  if (prof && threadIdx.x == 0) {
+    atomicAdd(&prof[2 * cls], (unsigned long long)(wall_clock64() - t0));
+    atomicAdd(&prof[2 * cls + 1], 1ull);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
   __shared__ __attribute__((aligned(16))) char pool[kPool];
   __shared__ int qslot;
@@ -337,8 +417,11 @@ __global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
       for (int j = 0; j < n; j++)
         for (int i = j + tid; i < n; i += 256) L[i + (int64_t)j * M.ldl] = M.A[i + (int64_t)j * M.lda];
     __syncthreads();
-    for (int t = M.t0; t < M.t1; t++)
+    for (int t = M.t0; t < M.t1; t++) {
+      const unsigned long long t0 = wall_clock64();
       run_task(prog.tasks[t], prog, L, M.ldl, ws, part, st, prog.scale_mode, pool);
+      prof_add(prog.prof, task_class(prog.tasks[t]), t0);
+    }
     __threadfence_block();
     __syncthreads();
     // the bodies record failures with L2 atomics: read them past the L1
@@ -361,16 +444,20 @@ __global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
       for (int c = 0; c < prog.nrhs; c++)
         for (int i = tid; i < n; i += 256) M.X[i + (int64_t)c * n] = M.B[i + (int64_t)c * n];
       __syncthreads();
-      wg_trsv(0, L, M.ldl, n, prog.nrhs, M.X, pool);
-      wg_trsv(1, L, M.ldl, n, prog.nrhs, M.X, pool);
+      unsigned long long t0 = wall_clock64();
+      wg_solve(L, M.ldl, n, prog.nrhs, M.X, pool);
+      prof_add(prog.prof, 8, t0);
       if (prog.max_iter > 0) {
         status = MPCHOL_NOT_CONVERGED_CODE;
         double prev = __longlong_as_double(0x7FF0000000000000ll);
         int grew = 0;
         for (int it = 1; it <= prog.max_iter; it++) {
-          wg_residual(M.A, M.lda, n, prog.nrhs, M.X, M.B, n, R, pool);
-          wg_trsv(0, L, M.ldl, n, prog.nrhs, R, pool);
-          wg_trsv(1, L, M.ldl, n, prog.nrhs, R, pool);
+          t0 = wall_clock64();
+          wg_resid(M.A, M.lda, n, prog.nrhs, M.X, M.B, n, R, pool);
+          prof_add(prog.prof, 9, t0);
+          t0 = wall_clock64();
+          wg_solve(L, M.ldl, n, prog.nrhs, R, pool);
+          prof_add(prog.prof, 8, t0);
           const double w = wg_update(n, prog.nrhs, M.X, R, pool);
           iters = it;
           corr = w;
@@ -403,14 +490,15 @@ __global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
   }
 }
 
-__global__ void k_queue_reset(unsigned int* q) {
+__global__ void k_queue_reset(unsigned int* q, unsigned long long* prof) {
   if (threadIdx.x == 0) *q = 0u;
+  if (prof && threadIdx.x < 20) prof[threadIdx.x] = 0ull;
 }
 
 }  // namespace
 
 hipError_t launch_batched(const BatchProgram& prog, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, prog.queue);
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, prog.queue, prog.prof);
   hipLaunchKernelGGL(k_batched, dim3(nwg), dim3(256), 0, s, prog);
   return hipGetLastError();
 }

@@ -71,6 +71,7 @@ struct Builder {
   const mpchol_tree& t;
   int64_t ldl;
   bool single_wg = false;
+  int tile_force = 0;
   int64_t next_node = 0;
   size_t ws_cursor = 0;   // bytes used by the current group of quantized copies
   int64_t part_cursor = 0;
@@ -221,7 +222,9 @@ struct Builder {
         int64_t tm = cdiv(g.m, 128);
         t128 += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, 128);
       }
-      if (single_wg) {
+      if (tile_force) {
+        L.tile = tile_force;
+      } else if (single_wg) {
         int mn = 1 << 30;
         for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
         L.tile = mn >= 128 ? 128 : 64;
@@ -348,7 +351,7 @@ struct Builder {
 
 }  // namespace
 
-void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg) {
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg, int tile) {
   P.n = n;
   P.ldl = ldl;
   P.tree = *t;
@@ -356,6 +359,7 @@ void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool sing
   P.tree.node_prec = nullptr;
   Builder B(P, P.tree, ldl);
   B.single_wg = single_wg;
+  B.tile_force = tile;
   B.potrf(0, n, 0);
   P.stats.n_launch = (int64_t)P.launches.size();
 }

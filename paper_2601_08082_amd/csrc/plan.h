@@ -48,7 +48,9 @@ int validate_tree(const mpchol_tree* t);
 std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t);
 // single_wg: the plan runs inside one workgroup (batched executor); GEMM
 // tiles are chosen for per-workgroup efficiency instead of chip occupancy.
-void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg = false);
+// tile: 0 automatic, 64 or 128 forces the GEMM output tile.
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg = false,
+                int tile = 0);
 int64_t split_rule(int64_t m, int32_t align);
 
 }  // namespace mpc

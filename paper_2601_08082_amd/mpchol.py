@@ -62,6 +62,11 @@ class CInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CTuneEntry(ct.Structure):
+    _fields_ = [("nmax", ct.c_int32), ("leaf", ct.c_int32), ("split_align", ct.c_int32),
+                ("tile", ct.c_int32)]
+
+
 def _load() -> ct.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
@@ -87,7 +92,7 @@ def _load() -> ct.CDLL:
                                       ct.POINTER(i64)]
     lib.mpchol_quantize.argtypes = [vp, i64, i64, vp, i64, i32, i32, vp, i64,
                                     ct.POINTER(dbl), vp]
-    lib.mpchol_set_tune_table.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32)]
+    lib.mpchol_set_tune_table.argtypes = [vp, i32, ct.POINTER(CTuneEntry)]
     lib.mpchol_profile.argtypes = [vp, ct.c_uint32]
     lib.mpchol_profile_read.argtypes = [vp, ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(i64)]
     lib.mpchol_version.restype = ct.c_char_p
@@ -275,14 +280,23 @@ class Context:
             raise RuntimeError("mpchol_profile_read failed")
         return {k: (ms[i], wk[i], nl[i]) for i, k in enumerate(PROF_KINDS)}
 
-    def set_tune_table(self, nmax: Sequence[int], leaf: Sequence[int]):
-        """Leaf size by system size for factor_batched (autotuner output)."""
-        k = len(nmax)
-        a = (ct.c_int32 * max(k, 1))(*nmax)
-        b = (ct.c_int32 * max(k, 1))(*leaf)
-        r = lib.mpchol_set_tune_table(self._h, k, a, b)
+    def set_tune_table(self, entries):
+        """Per-size plan choices for factor_batched: a list of
+        (nmax, leaf, split_align, tile) tuples (0 = the descriptor's / automatic),
+        nmax strictly increasing; [] clears the table."""
+        k = len(entries)
+        arr = (CTuneEntry * max(k, 1))(*[CTuneEntry(*map(int, e)) for e in entries])
+        r = lib.mpchol_set_tune_table(self._h, k, arr)
         if r != 0:
             raise ValueError(f"mpchol_set_tune_table: invalid argument {-r}")
+
+    def load_tune_table(self, path: str):
+        """Install a table written by the autotuner (JSON)."""
+        import json
+        with open(path) as f:
+            tab = json.load(f)
+        self.set_tune_table([(e["nmax"], e["leaf"], e.get("split_align", 0), e.get("tile", 0))
+                             for e in tab["entries"]])
 
     def factor_batched(self, A_list, L_list, ns, tree: Tree, B_list=None, X_list=None,
                        tol: float = 1e-13, max_iter: int = 20, stream=None):

@@ -122,17 +122,19 @@ def test_batched_tune_table_and_replay(M, ctx):
     sizes = [60, 150, 300, 40]
     mats = [spdgen.gen_spd(n, 2.0, 0.0, seed=n + 1) for n in sizes]
     t = M.Tree(leaf=64, offdiag=[M.F16], split_align=32)
-    ctx.set_tune_table([64, 200], [32, 48])
+    ctx.set_tune_table([(64, 32, 0, 0), (200, 48, 16, 64)])
     try:
         A, L, B, X, Bh = _batch(M, mats, 3)
         for rep in range(2):                     # second call replays the captured graph
             st, infos = ctx.factor_batched(A, L, sizes, t, B, X)
             assert st == 0
         for i, n in enumerate(sizes):
-            leaf = 32 if n <= 64 else (48 if n <= 200 else 64)
-            Le, _, _ = O.factor(mats[i], tree=_otree(t, leaf))
+            leaf, al = (32, 32) if n <= 64 else ((48, 16) if n <= 200 else (64, 32))
+            ot = _otree(t, leaf)
+            ot.split_align = al
+            Le, _, _ = O.factor(mats[i], tree=ot)
             Lg = M.from_device_cm(L[i])
             be_g, be_e = O.backward_error(mats[i], Lg), O.backward_error(mats[i], Le)
             assert 0.5 <= be_g / be_e <= 2.0, (n, leaf, be_g, be_e)
     finally:
-        ctx.set_tune_table([], [])
+        ctx.set_tune_table([])
