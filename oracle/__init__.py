@@ -53,6 +53,8 @@ def _load():
     i64 = ct.c_int64
     lib.orc_round.argtypes = [ct.c_double, ct.c_int32]
     lib.orc_round.restype = ct.c_double
+    lib.orc_round_array.argtypes = [dp, ct.c_int64, ct.c_int32, dp]
+    lib.orc_round_array.restype = None
     lib.orc_scale.argtypes = [ct.c_double, ct.c_int32, ct.c_int32]
     lib.orc_scale.restype = ct.c_double
     lib.orc_rmax.argtypes = [ct.c_int32]
@@ -129,8 +131,10 @@ def round_to(x: float, prec: int) -> float:
 
 
 def round_array(x: np.ndarray, prec: int) -> np.ndarray:
-    f = _load().orc_round
-    return np.array([f(float(v), prec) for v in np.ravel(x)]).reshape(np.shape(x))
+    a = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.empty_like(a)
+    _load().orc_round_array(_dp(a), a.size, prec, _dp(out))
+    return out.reshape(np.shape(x))
 
 
 def scale(maxabs: float, prec: int, scale_mode: int = 0) -> float:

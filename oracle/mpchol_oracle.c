@@ -84,6 +84,10 @@ double orc_round(double x, int32_t prec) {
   return copysign(r, x);
 }
 
+void orc_round_array(const double* x, int64_t count, int32_t prec, double* out) {
+  for (int64_t i = 0; i < count; i++) out[i] = orc_round(x[i], prec);
+}
+
 double orc_scale(double maxabs, int32_t prec, int32_t scale_mode) {
   if (prec == ORC_F64) return 1.0;
   if (!(maxabs > 0.0) || isinf(maxabs)) return 1.0;   /* zero block or non-finite */

@@ -36,6 +36,8 @@ typedef struct {
 /* Round x to the format's nearest value (ties to even, gradual underflow),
  * returned as a double.  prec = ORC_F16 / ORC_E4M3 / ORC_F32; F64 returns x. */
 double orc_round(double x, int32_t prec);
+/* out[i] = orc_round(x[i], prec) for i < count. */
+void orc_round_array(const double* x, int64_t count, int32_t prec, double* out);
 /* Power-of-two operand scale for a block with max-abs entry maxabs. */
 double orc_scale(double maxabs, int32_t prec, int32_t scale_mode);
 /* Largest finite value of the format. */
