@@ -250,6 +250,74 @@ typedef struct {
  */
 int mpchol_set_tune_table(mpchol_ctx ctx, int32_t count, const mpchol_tune_entry* table);
 
+/* ------------------------------------------------------------------------
+ * Learned per-node precision policy.  The paper fixes one precision per
+ * recursion level (Section 3.3) and names learned precision selection as
+ * future work (Section 6).  Here each internal Tree-POTRF node (Algorithm 1;
+ * order m > leaf, numbered in preorder like mpchol_tree.node_prec) gets the
+ * precision of its Tree-TRSM / Tree-SYRK updates from a 5-64-64-4 perceptron
+ * (ReLU, softmax over {E4M3, F16, F32, F64}) evaluated on five features of the
+ * input matrix, computed before the factorization so the plan stays static:
+ *   f1 = log2(rms(A21) / sqrt(mean diagonal of the node))   (-64 if A21 = 0)
+ *   f2 = log2(max|A21| / rms(A21))                          (0 if A21 = 0)
+ *   f3 = log2(min over the node's rows i of a_ii / sum_{j!=i} |a_ij|), full
+ *        rows of the symmetric A, clamped to [-30, 30]
+ *   f4 = depth,  f5 = log2(m1)      (A21 = A[i0+m1 : i0+m, i0 : i0+m1])
+ * Parameters: MPCHOL_MLP_PARAMS floats, mu(5) sigma(5) W1(64x5) b1(64)
+ * W2(64x64) b2(64) W3(4x64) b3(4), matrices row-major (out x in); the input
+ * is standardized as (x - mu) / sigma.  All buffers below are device memory
+ * unless named _host.
+ * ------------------------------------------------------------------------ */
+#define MPCHOL_MLP_PARAMS 4814
+
+/* Internal nodes of an order-n factorization under `tree` (host only).
+ * table_host: NULL, or room for 4 int64 per node: i0, m, m1, depth.
+ * Returns the node count, or a negative argument error (-1 n < 0; -2 tree). */
+int64_t mpchol_policy_nodes(int64_t n, const mpchol_tree* tree, int64_t* table_host);
+
+/* feat (nodes x 5 floats) <- the features of every node of A (lower
+ * triangle, column-major, lda >= n).  Reads the lower triangle twice.
+ * Asynchronous on `stream`.  Errors: -2 n; -3 A; -4 lda; -5 tree; -6 feat. */
+int mpchol_policy_features(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
+                           const mpchol_tree* tree, float* feat, void* stream);
+
+/* Training labels from an FP64 factor L of A.  For node k with X = L21 and
+ * p in {E4M3, F16, F32}: e(p) = 2 ||X||_F ||X - s Q_p(X/s)||_F / ||A_node||_F
+ * (s: the block's power-of-two scale under scale_mode, Section 3.4; A_node
+ * the node's symmetric diagonal block); label = the cheapest p with
+ * e(p) <= tau * m1_k^2 / sum_j m1_j^2, else F64.
+ * err: NULL or nodes x 3 doubles; labels: nodes int32.  Asynchronous.
+ * Errors: -2 n; -3 A; -4 lda; -5 L; -6 ldl; -7 tree; -8 tau <= 0;
+ * -9 scale_mode; -10 labels. */
+int mpchol_policy_labels(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
+                         const double* L, int64_t ldl, const mpchol_tree* tree, double tau,
+                         int32_t scale_mode, double* err, int32_t* labels, void* stream);
+
+/* Forward pass on rows x 5 features X (row-major): probs (rows x 4, or
+ * NULL) and the argmax class (rows, or NULL).  FP32.  Asynchronous.
+ * Errors: -2 rows < 0; -3 X; -4 params. */
+int mpchol_mlp_forward(mpchol_ctx ctx, int64_t rows, const float* X, const float* params,
+                       float* probs, int32_t* cls, void* stream);
+
+/* One training step on the mean cross-entropy of (X, y): the gradient of the
+ * trained parameters (everything but mu, sigma) summed over the rows in a
+ * fixed order, then, if lr > 0, one Adam step (beta 0.9 / 0.999, eps 1e-8,
+ * bias-corrected with `step` >= 1) on params with moments m, v (each
+ * MPCHOL_MLP_PARAMS floats).  loss: NULL or 1 float (before the step);
+ * grad: NULL or MPCHOL_MLP_PARAMS floats.  Asynchronous.
+ * Errors: -2 rows < 1; -3 X; -4 y; -5 params; -6 m / v; -7 step < 1. */
+int mpchol_mlp_train_step(mpchol_ctx ctx, int64_t rows, const float* X, const int32_t* y,
+                          float* params, float* m, float* v, int32_t step, float lr,
+                          float* loss, float* grad, void* stream);
+
+/* Features + forward pass + argmax for every node of A, copied to the host
+ * as a node_prec array (mpchol_policy_nodes entries) for the descriptor of a
+ * following mpchol_factor.  Synchronizes the stream.
+ * Errors: -2 n; -3 A; -4 lda; -5 tree; -6 params; -7 node_prec_host. */
+int mpchol_policy_choose(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
+                         const mpchol_tree* tree, const float* params, int8_t* node_prec_host,
+                         void* stream);
+
 /* Human-readable build/version string (static storage). */
 const char* mpchol_version(void);
 

@@ -16,6 +16,7 @@
 #include "internal.h"
 #include "numfmt.h"
 #include "plan.h"
+#include "policy.h"
 
 using namespace mpc;
 
@@ -67,6 +68,8 @@ struct mpchol_ctx_s {
     hipGraph_t graph = nullptr;
     hipStream_t cap = nullptr;
   } bt;
+  // policy buffers (features, labels, training), grown on demand
+  std::vector<std::pair<void*, size_t>> pbuf;
 };
 
 static void free_batch(mpchol_ctx c) {
@@ -259,6 +262,89 @@ static int status_from(const DevStatus& h, mpchol_info* info) {
 }
 
 // the tune-table entry for a system of order n (NULL: the descriptor applies)
+// Device buffer `slot` of the policy path with at least `bytes` (grown after
+// the device has drained, so no queued kernel still uses the old one).
+static void* pol_buf(mpchol_ctx c, size_t slot, size_t bytes) {
+  if (c->pbuf.size() <= slot) c->pbuf.resize(slot + 1, {nullptr, 0});
+  auto& b = c->pbuf[slot];
+  if (b.second >= bytes && b.first) return b.first;
+  if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+  if (b.first) (void)hipFree(b.first);
+  b = {nullptr, 0};
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+  b = {p, std::max<size_t>(bytes, 256)};
+  return p;
+}
+
+static void add_stat_job(std::vector<StatJob>& jobs, int& parts, int64_t r0, int64_t c0, int64_t rows,
+                         int64_t cols, int mode, int node) {
+  StatJob j{};
+  j.r0 = r0;
+  j.c0 = c0;
+  j.rows = (int32_t)rows;
+  j.cols = (int32_t)cols;
+  j.mode = mode;
+  j.node = node;
+  const int64_t np = std::max<int64_t>(1, std::min<int64_t>(128, cols));
+  j.cpw = (int32_t)((cols + np - 1) / np);
+  j.nparts = (int32_t)((cols + j.cpw - 1) / j.cpw);
+  j.part0 = parts;
+  j.wg_start = parts;
+  parts += j.nparts;
+  jobs.push_back(j);
+}
+
+struct PolicyTables {
+  std::vector<PolicyNodeRec> rec;
+  std::vector<PNode> nodes;
+};
+
+static void policy_tables(int64_t n, const mpchol_tree* t, PolicyTables& T) {
+  tree_nodes(n, t, T.rec);
+  T.nodes.clear();
+  for (const PolicyNodeRec& r : T.rec)
+    T.nodes.push_back(PNode{r.i0, (int32_t)r.m, (int32_t)r.m1, r.depth, 0});
+}
+
+template <typename T>
+static int upload_async(mpchol_ctx c, size_t slot, const std::vector<T>& v, T** out, hipStream_t s) {
+  *out = (T*)pol_buf(c, slot, sizeof(T) * std::max<size_t>(1, v.size()));
+  if (!*out) return MPCHOL_HIP_ERROR;
+  if (!v.empty())
+    HIPCHK(hipMemcpyAsync(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+  // the host vector must outlive the copy
+  HIPCHK(hipStreamSynchronize(s));
+  return 0;
+}
+
+// Features of every node of A into feat (device).
+static int policy_features(mpchol_ctx c, int64_t n, const double* A, int64_t lda,
+                           const PolicyTables& T, float* feat, hipStream_t s) {
+  const int nn = (int)T.nodes.size();
+  if (nn == 0) return 0;
+  std::vector<StatJob> jobs;
+  int parts = 0;
+  for (int k = 0; k < nn; k++) {
+    const PNode& N = T.nodes[k];
+    add_stat_job(jobs, parts, N.i0 + N.m1, N.i0, N.m - N.m1, N.m1, 0, k);
+  }
+  const int64_t nstrip = (n + 63) / 64;
+  double* rowpart = (double*)pol_buf(c, 0, sizeof(double) * (size_t)(nstrip * n));
+  double* colsum = (double*)pol_buf(c, 1, sizeof(double) * (size_t)n);
+  double* ratio = (double*)pol_buf(c, 2, sizeof(double) * (size_t)n);
+  double* dparts = (double*)pol_buf(c, 3, sizeof(double) * 4 * (size_t)parts);
+  if (!rowpart || !colsum || !ratio || !dparts) return MPCHOL_HIP_ERROR;
+  PNode* dn = nullptr;
+  StatJob* dj = nullptr;
+  if (upload_async(c, 4, T.nodes, &dn, s) || upload_async(c, 5, jobs, &dj, s)) return MPCHOL_HIP_ERROR;
+  HIPCHK(launch_rowabs(A, lda, n, rowpart, colsum, s));
+  HIPCHK(launch_row_ratio(A, lda, n, rowpart, colsum, ratio, s));
+  HIPCHK(launch_stats(A, lda, dj, (int)jobs.size(), parts, nullptr, dparts, s));
+  HIPCHK(launch_node_features(dn, nn, A, lda, dj, dparts, ratio, feat, s));
+  return 0;
+}
+
 static const mpchol_tune_entry* tuned(mpchol_ctx c, int64_t n) {
   for (const mpchol_tune_entry& e : c->tune)
     if (n <= e.nmax) return &e;
@@ -276,6 +362,143 @@ static int dev_upload(std::vector<void*>& keep, T** dptr, const std::vector<T>& 
 }
 
 extern "C" {
+
+
+int64_t mpchol_policy_nodes(int64_t n, const mpchol_tree* tree, int64_t* table) {
+  if (n < 0) return -1;
+  if (validate_tree(tree)) return -2;
+  std::vector<PolicyNodeRec> rec;
+  tree_nodes(n, tree, rec);
+  if (table)
+    for (size_t k = 0; k < rec.size(); k++) {
+      table[4 * k + 0] = rec[k].i0;
+      table[4 * k + 1] = rec[k].m;
+      table[4 * k + 2] = rec[k].m1;
+      table[4 * k + 3] = rec[k].depth;
+    }
+  return (int64_t)rec.size();
+}
+
+int mpchol_policy_features(mpchol_ctx c, int64_t n, const double* A, int64_t lda,
+                           const mpchol_tree* tree, float* feat, void* stream) {
+  if (!c) return -1;
+  if (n < 0 || n > (int64_t)1 << 31) return -2;
+  if (n > 0 && !A) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (validate_tree(tree)) return -5;
+  PolicyTables T;
+  policy_tables(n, tree, T);
+  if (!T.nodes.empty() && !feat) return -6;
+  HIPCHK(hipSetDevice(c->device));
+  return policy_features(c, n, A, lda, T, feat, (hipStream_t)stream);
+}
+
+int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, const double* L,
+                         int64_t ldl, const mpchol_tree* tree, double tau, int32_t scale_mode,
+                         double* err, int32_t* labels, void* stream) {
+  if (!c) return -1;
+  if (n < 0 || n > (int64_t)1 << 31) return -2;
+  if (n > 0 && !A) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (n > 0 && !L) return -5;
+  if (ldl < std::max<int64_t>(1, n)) return -6;
+  if (validate_tree(tree)) return -7;
+  if (!(tau > 0.0)) return -8;
+  if (scale_mode != 0 && scale_mode != 1) return -9;
+  PolicyTables T;
+  policy_tables(n, tree, T);
+  const int nn = (int)T.nodes.size();
+  if (nn == 0) return 0;
+  if (!labels) return -10;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<StatJob> xj, xj2, aj;
+  int xparts = 0, xparts2 = 0, aparts = 0;
+  double sum_s2 = 0.0;
+  for (int k = 0; k < nn; k++) {
+    const PNode& N = T.nodes[k];
+    add_stat_job(xj, xparts, N.i0 + N.m1, N.i0, N.m - N.m1, N.m1, 0, k);
+    add_stat_job(xj2, xparts2, N.i0 + N.m1, N.i0, N.m - N.m1, N.m1, 2, k);
+    add_stat_job(aj, aparts, N.i0, N.i0, N.m, N.m, 1, k);
+    sum_s2 += (double)N.m1 * (double)N.m1;
+  }
+  double* dx = (double*)pol_buf(c, 6, sizeof(double) * 4 * (size_t)xparts);
+  double* da = (double*)pol_buf(c, 7, sizeof(double) * 4 * (size_t)aparts);
+  double* sc = (double*)pol_buf(c, 8, sizeof(double) * 3 * (size_t)nn);
+  if (!dx || !da || !sc) return MPCHOL_HIP_ERROR;
+  PNode* dn = nullptr;
+  StatJob *dxj = nullptr, *dxj2 = nullptr, *daj = nullptr;
+  if (upload_async(c, 4, T.nodes, &dn, s) || upload_async(c, 9, xj, &dxj, s) ||
+      upload_async(c, 10, xj2, &dxj2, s) || upload_async(c, 11, aj, &daj, s))
+    return MPCHOL_HIP_ERROR;
+  HIPCHK(launch_stats(L, ldl, dxj, nn, xparts, nullptr, dx, s));
+  HIPCHK(launch_node_scales(nn, dxj, dx, scale_mode, sc, s));
+  HIPCHK(launch_stats(L, ldl, dxj2, nn, xparts2, sc, dx, s));
+  HIPCHK(launch_stats(A, lda, daj, nn, aparts, nullptr, da, s));
+  HIPCHK(launch_node_labels(dn, nn, dxj2, dx, daj, da, tau, sum_s2, err, labels, s));
+  return 0;
+}
+
+int mpchol_mlp_forward(mpchol_ctx c, int64_t rows, const float* X, const float* params,
+                       float* probs, int32_t* cls, void* stream) {
+  if (!c) return -1;
+  if (rows < 0) return -2;
+  if (rows > 0 && !X) return -3;
+  if (!params) return -4;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_mlp_forward(rows, X, params, probs, cls, (hipStream_t)stream));
+  return 0;
+}
+
+int mpchol_mlp_train_step(mpchol_ctx c, int64_t rows, const float* X, const int32_t* y,
+                          float* params, float* m, float* v, int32_t step, float lr, float* loss,
+                          float* grad, void* stream) {
+  if (!c) return -1;
+  if (rows < 1 || rows > ((int64_t)1 << 31)) return -2;
+  if (!X) return -3;
+  if (!y) return -4;
+  if (!params) return -5;
+  if (lr > 0.f && (!m || !v)) return -6;
+  if (step < 1) return -7;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  const int nwg = (int)((rows + kMlpRows - 1) / kMlpRows);
+  float* gpart = (float*)pol_buf(c, 12, sizeof(float) * (size_t)kMlpTrained * (size_t)nwg);
+  float* lpart = (float*)pol_buf(c, 13, sizeof(float) * (size_t)nwg);
+  if (!gpart || !lpart) return MPCHOL_HIP_ERROR;
+  HIPCHK(launch_mlp_grad(rows, X, y, params, gpart, lpart, s));
+  HIPCHK(launch_mlp_adam(nwg, rows, gpart, lpart, params, m, v, step, lr, loss, grad, s));
+  return 0;
+}
+
+int mpchol_policy_choose(mpchol_ctx c, int64_t n, const double* A, int64_t lda,
+                         const mpchol_tree* tree, const float* params, int8_t* node_prec,
+                         void* stream) {
+  if (!c) return -1;
+  if (n < 0 || n > (int64_t)1 << 31) return -2;
+  if (n > 0 && !A) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (validate_tree(tree)) return -5;
+  if (!params) return -6;
+  PolicyTables T;
+  policy_tables(n, tree, T);
+  const int nn = (int)T.nodes.size();
+  if (nn == 0) return 0;
+  if (!node_prec) return -7;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  float* feat = (float*)pol_buf(c, 14, sizeof(float) * kMlpIn * (size_t)nn);
+  int32_t* cls = (int32_t*)pol_buf(c, 15, sizeof(int32_t) * (size_t)nn);
+  if (!feat || !cls) return MPCHOL_HIP_ERROR;
+  int r = policy_features(c, n, A, lda, T, feat, s);
+  if (r) return r;
+  HIPCHK(launch_mlp_forward(nn, feat, params, nullptr, cls, s));
+  std::vector<int32_t> h((size_t)nn);
+  HIPCHK(hipMemcpyAsync(h.data(), cls, sizeof(int32_t) * (size_t)nn, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < nn; k++) node_prec[k] = (int8_t)h[(size_t)k];
+  return 0;
+}
 
 const char* mpchol_version(void) { return "mpchol 0.1 (gfx950, HIP)"; }
 
@@ -313,6 +536,7 @@ int mpchol_destroy(mpchol_ctx c) {
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   free_batch(c);
   if (c->bt.cap) (void)hipStreamDestroy(c->bt.cap);
+  for (auto& b : c->pbuf) (void)hipFree(b.first);
   delete c;
   return 0;
 }

@@ -351,6 +351,20 @@ struct Builder {
 
 }  // namespace
 
+static void tree_nodes_rec(int64_t i0, int64_t m, int32_t depth, const mpchol_tree* t,
+                           std::vector<PolicyNodeRec>& out) {
+  if (m <= 0 || m <= t->leaf) return;
+  const int64_t m1 = split_rule(m, t->split_align);
+  out.push_back({i0, m, m1, depth});
+  tree_nodes_rec(i0, m1, depth + 1, t, out);
+  tree_nodes_rec(i0 + m1, m - m1, depth + 1, t, out);
+}
+
+void tree_nodes(int64_t n, const mpchol_tree* t, std::vector<PolicyNodeRec>& out) {
+  out.clear();
+  tree_nodes_rec(0, n, 0, t, out);
+}
+
 void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg, int tile) {
   P.n = n;
   P.ldl = ldl;

@@ -53,4 +53,13 @@ void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool sing
                 int tile = 0);
 int64_t split_rule(int64_t m, int32_t align);
 
+// Internal Tree-POTRF nodes (order > leaf) of an order-n factorization in
+// preorder: {i0, m, m1, depth} each.
+struct PolicyNodeRec {
+  int64_t i0;
+  int64_t m, m1;
+  int32_t depth;
+};
+void tree_nodes(int64_t n, const mpchol_tree* t, std::vector<PolicyNodeRec>& out);
+
 }  // namespace mpc

@@ -95,6 +95,16 @@ def _load() -> ct.CDLL:
     lib.mpchol_set_tune_table.argtypes = [vp, i32, ct.POINTER(CTuneEntry)]
     lib.mpchol_profile.argtypes = [vp, ct.c_uint32]
     lib.mpchol_profile_read.argtypes = [vp, ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(i64)]
+    lib.mpchol_policy_nodes.argtypes = [i64, ct.POINTER(CTree), ct.POINTER(i64)]
+    lib.mpchol_policy_nodes.restype = i64
+    lib.mpchol_policy_features.argtypes = [vp, i64, vp, i64, ct.POINTER(CTree), vp, vp]
+    lib.mpchol_policy_labels.argtypes = [vp, i64, vp, i64, vp, i64, ct.POINTER(CTree), dbl, i32,
+                                         vp, vp, vp]
+    lib.mpchol_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    lib.mpchol_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, ct.c_float, vp, vp,
+                                          vp]
+    lib.mpchol_policy_choose.argtypes = [vp, i64, vp, i64, ct.POINTER(CTree), vp,
+                                         ct.POINTER(ct.c_int8), vp]
     lib.mpchol_version.restype = ct.c_char_p
     return lib
 
@@ -280,6 +290,69 @@ class Context:
             raise RuntimeError("mpchol_profile_read failed")
         return {k: (ms[i], wk[i], nl[i]) for i, k in enumerate(PROF_KINDS)}
 
+    # ------------------------------------------------------------ learned policy
+    def policy_features(self, A_cm, n: int, tree: Tree, stream=None):
+        """(nodes, 5) float32 device tensor of per-node features."""
+        import torch
+        _check_cm(A_cm, "A")
+        nn = policy_nodes(n, tree).shape[0]
+        feat = torch.empty((max(nn, 1), MLP_IN), dtype=torch.float32, device=A_cm.device)
+        t, keep = tree.to_c()
+        r = lib.mpchol_policy_features(self._h, n, _ptr(A_cm), A_cm.shape[1], ct.byref(t),
+                                       feat.data_ptr(), _stream_handle(stream))
+        _raise(r, "mpchol_policy_features")
+        return feat[:nn]
+
+    def policy_labels(self, A_cm, L_cm, n: int, tree: Tree, tau: float = 1e-4,
+                      scale_mode: int = 1, stream=None):
+        """(labels int32 (nodes,), errors float64 (nodes, 3)) device tensors."""
+        import torch
+        nn = policy_nodes(n, tree).shape[0]
+        lab = torch.empty(max(nn, 1), dtype=torch.int32, device=A_cm.device)
+        err = torch.empty((max(nn, 1), 3), dtype=torch.float64, device=A_cm.device)
+        t, keep = tree.to_c()
+        r = lib.mpchol_policy_labels(self._h, n, _ptr(A_cm), A_cm.shape[1], _ptr(L_cm),
+                                     L_cm.shape[1], ct.byref(t), tau, scale_mode,
+                                     err.data_ptr(), lab.data_ptr(), _stream_handle(stream))
+        _raise(r, "mpchol_policy_labels")
+        return lab[:nn], err[:nn]
+
+    def mlp_forward(self, X, params, stream=None):
+        """(probs (rows, 4), classes (rows,)) for float32 features X (rows, 5)."""
+        import torch
+        rows = X.shape[0]
+        probs = torch.empty((max(rows, 1), MLP_OUT), dtype=torch.float32, device=X.device)
+        cls = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
+        r = lib.mpchol_mlp_forward(self._h, rows, X.data_ptr(), params.data_ptr(),
+                                   probs.data_ptr(), cls.data_ptr(), _stream_handle(stream))
+        _raise(r, "mpchol_mlp_forward")
+        return probs[:rows], cls[:rows]
+
+    def mlp_train_step(self, X, y, params, m, v, step: int, lr: float, want_grad: bool = False,
+                       stream=None):
+        """One gradient (+ Adam when lr > 0) step in place on params/m/v;
+        returns (loss tensor (1,), grad tensor or None)."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device) if want_grad else None
+        r = lib.mpchol_mlp_train_step(self._h, X.shape[0], X.data_ptr(), y.data_ptr(),
+                                      params.data_ptr(), m.data_ptr() if m is not None else None,
+                                      v.data_ptr() if v is not None else None, step, lr,
+                                      loss.data_ptr(), grad.data_ptr() if want_grad else None,
+                                      _stream_handle(stream))
+        _raise(r, "mpchol_mlp_train_step")
+        return loss, grad
+
+    def policy_choose(self, A_cm, n: int, tree: Tree, params, stream=None) -> list:
+        """Per-node precisions chosen by the perceptron (preorder node list)."""
+        nn = policy_nodes(n, tree).shape[0]
+        out = (ct.c_int8 * max(nn, 1))()
+        t, keep = tree.to_c()
+        r = lib.mpchol_policy_choose(self._h, n, _ptr(A_cm), A_cm.shape[1], ct.byref(t),
+                                     params.data_ptr(), out, _stream_handle(stream))
+        _raise(r, "mpchol_policy_choose")
+        return [int(out[i]) for i in range(nn)]
+
     def set_tune_table(self, entries):
         """Per-size plan choices for factor_batched: a list of
         (nmax, leaf, split_align, tile) tuples (0 = the descriptor's / automatic),
@@ -321,6 +394,30 @@ class Context:
         if r == HIP_ERROR:
             raise RuntimeError("mpchol_factor_batched: HIP error")
         return r, [infos[i].as_dict() for i in range(batch)]
+
+
+MLP_IN, MLP_H, MLP_OUT = 5, 64, 4
+MLP_PARAMS = 4814
+
+
+def _raise(r: int, name: str):
+    if r < 0:
+        raise ValueError(f"{name}: invalid argument {-r}")
+    if r == HIP_ERROR:
+        raise RuntimeError(f"{name}: HIP error")
+    if r != 0:
+        raise RuntimeError(f"{name}: status {r}")
+
+
+def policy_nodes(n: int, tree: Tree):
+    """(nodes, 4) int64 array: i0, m, m1, depth of each internal node (preorder)."""
+    t, keep = tree.to_c()
+    k = lib.mpchol_policy_nodes(n, ct.byref(t), None)
+    if k < 0:
+        raise ValueError(f"mpchol_policy_nodes: invalid argument {-k}")
+    tab = (ct.c_int64 * max(4 * k, 1))()
+    lib.mpchol_policy_nodes(n, ct.byref(t), tab)
+    return np.array(tab[:4 * k], dtype=np.int64).reshape(k, 4)
 
 
 def version() -> str:

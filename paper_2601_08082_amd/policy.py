@@ -1,0 +1,201 @@
+"""Training and use of the learned per-node precision policy.
+
+Every step runs in the library's kernels (mpchol_policy_features,
+mpchol_policy_labels, mpchol_mlp_train_step, mpchol_policy_choose); this
+module only generates the synthetic training matrices, shuffles minibatches
+on the host and strings the calls together.
+
+Training set (one row per internal Tree-POTRF node): `count` matrices of the
+seeded generator with n log-uniform in [nmin, nmax] (multiples of 256) and
+dominance ratio log-uniform in [rmin, rmax]; features from A, labels from an
+FP64 factor of A (the cheapest precision whose quantization error of the
+node's L21 block fits the node's share of the error budget tau).
+
+Inference: the perceptron picks each node's precision; the factor runs with
+scale_mode 1 (power-of-two scaling both ways, needed by E4M3).  If the
+factor or the refined solve fails, the fallback chain retries with the fixed
+paper tree and then with the all-FP64 tree.
+
+    python -m paper_2601_08082_amd.policy --count 20000 --out paper_2601_08082_amd/policy_mi355x.npy
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import mpchol as M
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "policy_mi355x.npy")
+
+
+def policy_tree(leaf: int = 256, split_align: int = 1) -> "M.Tree":
+    """Descriptor the policy's node numbering refers to (per-node override on top)."""
+    return M.Tree(leaf=leaf, offdiag=[M.F16], leaf_prec=M.F64, split_align=split_align,
+                  scale_mode=1)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-initialised float32 parameter vector (mu = 0, sigma = 1)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(M.MLP_PARAMS, dtype=np.float32)
+    o = 0
+    p[o:o + 5] = 0.0
+    p[o + 5:o + 10] = 1.0
+    o = 10
+    for fan_out, fan_in in ((64, 5), (64, 64), (4, 64)):
+        p[o:o + fan_out * fan_in] = rng.normal(0, math.sqrt(2.0 / fan_in), fan_out * fan_in)
+        o += fan_out * fan_in + fan_out
+    return p
+
+
+def training_recipe(count: int, nmin: int = 1024, nmax: int = 8192, rmin: float = 1.05,
+                    rmax: float = 10.0, seed: int = 5):
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(math.log(nmin), math.log(nmax), count))
+    ns = np.clip(np.rint(ns / 256.0) * 256, nmin, nmax).astype(np.int64)
+    ratios = np.exp(rng.uniform(math.log(rmin), math.log(rmax), count))
+    return [int(n) for n in ns], [float(r) for r in ratios], [seed * 100_003 + i for i in range(count)]
+
+
+def build_dataset(ctx, ns, ratios, seeds, tree, tau: float = 1e-4, log_every: int = 0):
+    """Features (rows, 5) float32 and labels (rows,) int32, as device tensors."""
+    import torch
+    from . import spdgen_gpu
+    t64 = M.Tree(leaf=tree.leaf, offdiag=[M.F64], leaf_prec=M.F64, split_align=tree.split_align)
+    feats, labs = [], []
+    t0 = time.time()
+    for i, (n, r, sd) in enumerate(zip(ns, ratios, seeds)):
+        A = spdgen_gpu.gen_spd(n, r, 0.0, seed=sd)
+        L, info = ctx.factor(A, n, t64)
+        if info["status"] != 0:
+            raise RuntimeError(f"training matrix {i} (n={n}, ratio={r}): FP64 factor failed {info}")
+        feats.append(ctx.policy_features(A, n, tree))
+        lab, _ = ctx.policy_labels(A, L, n, tree, tau=tau, scale_mode=1)
+        labs.append(lab)
+        del A, L
+        if log_every and (i + 1) % log_every == 0:
+            print(f"[policy] dataset {i + 1}/{len(ns)} matrices, {time.time() - t0:.1f} s", flush=True)
+    X = torch.cat(feats)
+    y = torch.cat(labs)
+    torch.cuda.synchronize()
+    return X, y
+
+
+def train(ctx, X, y, epochs: int = 30, batch: int = 1024, lr: float = 3e-3, seed: int = 0,
+          params0: np.ndarray | None = None, log_every: int = 0):
+    """Adam on the mean cross-entropy; returns (params device tensor, per-epoch mean losses)."""
+    import torch
+    dev = X.device
+    Xh = X.cpu().numpy().astype(np.float64)
+    p = init_params(seed) if params0 is None else params0.astype(np.float32).copy()
+    # standardization from the data (host, 5 numbers each)
+    mu = Xh.mean(axis=0)
+    sd = Xh.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    p[0:5] = mu
+    p[5:10] = sd
+    params = torch.from_numpy(p).to(dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    rng = np.random.default_rng(seed + 1)
+    rows = X.shape[0]
+    Xc, yc = X.cpu(), y.cpu()
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(rows))
+        Xs = Xc[perm].contiguous().to(dev)
+        ys = yc[perm].contiguous().to(dev)
+        losses = []
+        for b0 in range(0, rows, batch):
+            b1 = min(rows, b0 + batch)
+            step += 1
+            loss, _ = ctx.mlp_train_step(Xs[b0:b1], ys[b0:b1], params, m, v, step, lr)
+            losses.append(loss)
+        hist.append(float(torch.stack(losses).mean().item()))
+        if log_every and (ep + 1) % log_every == 0:
+            print(f"[policy] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}", flush=True)
+    return params, hist
+
+
+def accuracy(ctx, X, y, params) -> float:
+    _, cls = ctx.mlp_forward(X, params)
+    return float((cls == y).float().mean().item())
+
+
+def load_params(path: str = DEFAULT_WEIGHTS, device="cuda"):
+    import torch
+    p = np.load(path)
+    if p.shape != (M.MLP_PARAMS,) or p.dtype != np.float32:
+        raise ValueError(f"{path}: expected float32[{M.MLP_PARAMS}]")
+    return torch.from_numpy(p).to(device)
+
+
+def solve_with_policy(ctx, A, B, n: int, params, tree=None, tol: float = 1e-13,
+                      max_iter: int = 20, fixed=None):
+    """Factor with the learned per-node precisions and refine; on failure fall
+    back to the fixed tree, then to all-FP64.  Returns (X, info dict)."""
+    tree = tree or policy_tree()
+    fixed = fixed or M.Tree(leaf=tree.leaf, offdiag=[M.F16], leaf_prec=M.F64,
+                            split_align=tree.split_align)
+    choice = ctx.policy_choose(A, n, tree, params)
+    learned = M.Tree(leaf=tree.leaf, offdiag=list(tree.offdiag), leaf_prec=tree.leaf_prec,
+                     split_align=tree.split_align, scale_mode=1, node_prec=choice)
+    chain = [("learned", learned), ("fixed", fixed),
+             ("fp64", M.Tree(leaf=tree.leaf, offdiag=[M.F64], split_align=tree.split_align))]
+    fallbacks = 0
+    for name, t in chain:
+        L, finfo = ctx.factor(A, n, t)
+        if finfo["status"] == 0:
+            X, sinfo = ctx.solve(L, B, n, A_cm=A, tol=tol, max_iter=max_iter)
+            if sinfo["status"] == 0:
+                return X, {"used": name, "fallbacks": fallbacks, "node_prec": choice,
+                           "ir_iters": sinfo["ir_iters"], "factor": finfo, "solve": sinfo}
+        fallbacks += 1
+    raise RuntimeError("every tree of the fallback chain failed")
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--count", type=int, default=20000)
+    ap.add_argument("--nmin", type=int, default=1024)
+    ap.add_argument("--nmax", type=int, default=8192)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--tau", type=float, default=1e-4)
+    ap.add_argument("--leaf", type=int, default=256)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    args = ap.parse_args(argv)
+    import torch
+    ctx = M.Context(0)
+    tree = policy_tree(args.leaf)
+    ns, ratios, seeds = training_recipe(args.count, args.nmin, args.nmax)
+    t0 = time.time()
+    X, y = build_dataset(ctx, ns, ratios, seeds, tree, args.tau, log_every=max(1, args.count // 20))
+    counts = np.bincount(y.cpu().numpy(), minlength=4)
+    print(f"[policy] {X.shape[0]} nodes, label counts E4M3/F16/F32/F64 = {counts.tolist()}, "
+          f"{time.time() - t0:.1f} s", flush=True)
+    nv = max(1, args.count // 10)
+    vns, vr, vs = training_recipe(nv, args.nmin, args.nmax, seed=6)
+    Xv, yv = build_dataset(ctx, vns, vr, vs, tree, args.tau)
+    params, hist = train(ctx, X, y, args.epochs, args.batch, args.lr,
+                         log_every=max(1, args.epochs // 10))
+    print(f"[policy] train accuracy {accuracy(ctx, X, y, params):.4f}, validation accuracy "
+          f"{accuracy(ctx, Xv, yv, params):.4f} ({Xv.shape[0]} nodes of {nv} held-out matrices), "
+          f"final loss {hist[-1]:.4f}", flush=True)
+    np.save(args.out, params.cpu().numpy().astype(np.float32))
+    print(f"[policy] wrote {args.out}", flush=True)
+    ctx.close()
+    torch.cuda.synchronize()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
