@@ -250,6 +250,18 @@ typedef struct {
  */
 int mpchol_set_tune_table(mpchol_ctx ctx, int32_t count, const mpchol_tune_entry* table);
 
+/*
+ * Backward error of a factor (the error norm the paper reports, Section 4):
+ * norms_host[0] = ||A - L L^T||_F and norms_host[1] = ||A||_F over the full
+ * symmetric matrix, from the lower triangles of A and L (L's upper triangle
+ * is never read).  FP64 on the device, deterministic; its own rounding is
+ * about sqrt(n) u ||A||, so it resolves backward errors above ~1e-14.
+ * Synchronizes the stream.
+ * Errors: -2 n < 0; -3 A; -4 lda; -5 L; -6 ldl; -7 norms_host.
+ */
+int mpchol_backward_error(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda, const double* L,
+                          int64_t ldl, double* norms_host, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned per-node precision policy.  The paper fixes one precision per
  * recursion level (Section 3.3) and names learned precision selection as

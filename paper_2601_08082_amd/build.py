@@ -15,7 +15,7 @@ GENLIB = os.path.join(HERE, "libspdgen.so")
 ARCH = os.environ.get("MPCHOL_ARCH", "gfx950")
 
 SOURCES = ["k_quant.hip", "k_gemm.hip", "k_leaf.hip", "k_solve.hip", "k_batched.hip", "k_policy.hip",
-           "plan.cpp", "capi.cpp"]
+           "k_check.hip", "plan.cpp", "capi.cpp"]
 # the leaf kernels round every a*b and every subtraction separately, in the
 # order of the textbook elimination
 EXTRA = {"k_leaf.hip": ["-ffp-contract=off"], "k_batched.hip": ["-ffp-contract=off"]}

@@ -41,6 +41,8 @@ struct mpchol_ctx_s {
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
   int64_t rbuf_count = 0;
+  double* resw = nullptr;     // residual tile partials
+  size_t resw_bytes = 0;
   double* npart = nullptr;    // norm partials (device)
   double* hnpart = nullptr;   // norm partials (pinned host)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -364,6 +366,27 @@ static int dev_upload(std::vector<void*>& keep, T** dptr, const std::vector<T>& 
 extern "C" {
 
 
+int mpchol_backward_error(mpchol_ctx c, int64_t n, const double* A, int64_t lda, const double* L,
+                          int64_t ldl, double* norms, void* stream) {
+  if (!c) return -1;
+  if (n < 0 || n > (int64_t)1 << 31) return -2;
+  if (n > 0 && !A) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (n > 0 && !L) return -5;
+  if (ldl < std::max<int64_t>(1, n)) return -6;
+  if (!norms) return -7;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  const int64_t nt = llt_tiles(n);
+  double* parts = (double*)pol_buf(c, 16, sizeof(double) * 2 * (size_t)std::max<int64_t>(1, nt));
+  double* out = (double*)pol_buf(c, 17, sizeof(double) * 2);
+  if (!parts || !out) return MPCHOL_HIP_ERROR;
+  HIPCHK(launch_llt_resid(n, A, lda, L, ldl, parts, out, s));
+  HIPCHK(hipMemcpyAsync(norms, out, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return 0;
+}
+
 int64_t mpchol_policy_nodes(int64_t n, const mpchol_tree* tree, int64_t* table) {
   if (n < 0) return -1;
   if (validate_tree(tree)) return -2;
@@ -527,6 +550,7 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
+  if (c->resw) (void)hipFree(c->resw);
   if (c->npart) (void)hipFree(c->npart);
   if (c->hnpart) (void)hipHostFree(c->hnpart);
   if (c->dst) (void)hipFree(c->dst);
@@ -627,6 +651,15 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
       HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
       c->rbuf_count = n * nrhs;
     }
+    const size_t wb = residual_work_bytes(n, (int)std::min<int64_t>(kMaxRhs, nrhs));
+    if (c->resw_bytes < wb) {
+      HIPCHK(hipStreamSynchronize(s));
+      if (c->resw) HIPCHK(hipFree(c->resw));
+      c->resw = nullptr;
+      c->resw_bytes = 0;
+      HIPCHK(hipMalloc((void**)&c->resw, wb));
+      c->resw_bytes = wb;
+    }
     double* R = c->rbuf;
     double prev = INFINITY;
     int grew = 0;
@@ -637,7 +670,7 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
         int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_RESIDUAL,
                                            (double)n * (n + 1) / 2 * 8.0, s) : -1;
         HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
-                               s));
+                               c->resw, s));
         prof_end(c, pk, s);
       }
       r = chol_solve_inplace(c, n, nrhs, L, ldl, R, n, s);

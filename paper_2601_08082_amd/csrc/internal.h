@@ -83,14 +83,23 @@ hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64
 // Solve / refinement kernels.
 hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs,
                        double* X, int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s);
+// R = B - A X (A symmetric, lower stored, read once); work holds
+// residual_work_bytes(n, nrhs) bytes of tile partials.
+size_t residual_work_bytes(int64_t n, int nrhs);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
-                           hipStream_t s);
+                           double* work, hipStream_t s);
 hipError_t launch_update_norms(int64_t n, int nrhs, double* X, int64_t ldx, const double* D,
                                int64_t ldd, double* part, int nparts, double* out,
                                hipStream_t s);
 hipError_t launch_copy_cols(int64_t n, int nrhs, const double* src, int64_t lds, double* dst,
                             int64_t ldd, hipStream_t s);
 hipError_t launch_ticket_reset(DevStatus* st, hipStream_t s);
+
+// Backward-error check: number of 64 x 64 lower tiles (partials) and the
+// launch writing out[0] = ||A - L L^T||_F, out[1] = ||A||_F.
+int64_t llt_tiles(int64_t n);
+hipError_t launch_llt_resid(int64_t n, const double* A, int64_t lda, const double* L, int64_t ldl,
+                            double* parts, double* out, hipStream_t s);
 
 }  // namespace mpc

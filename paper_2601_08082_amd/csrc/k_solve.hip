@@ -13,8 +13,8 @@ constexpr int NB = 64;          // block rows per workgroup
 constexpr int MAXRHS = 16;      // right-hand sides per launch (the host splits wider B)
 constexpr long kSpinLimit = 1L << 22;  // ~0.2 s of sleeps; real waits are microseconds
 
-__device__ inline unsigned int atomic_load_acq(unsigned int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline unsigned int atomic_load_rlx(unsigned int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline double coherent_load(const double* p) {
   unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
@@ -31,13 +31,15 @@ __device__ inline double bcast(double v, int src) {
 }
 
 // Wait until *done > k.  Returns false (and flags st->wait_timeout) when the
-// bounded spin gives up, so that every wave always exits.
+// bounded spin gives up, so that every wave always exits.  The spin uses
+// relaxed loads and one acquire fence at the end: an acquire per poll would
+// invalidate the L2 of the polling die on every iteration.
 __device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* st) {
   __shared__ int ok;
   if (threadIdx.x == 0) {
     long spins = 0;
     ok = 1;
-    while (atomic_load_acq(done) <= k) {
+    while (atomic_load_rlx(done) <= k) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) {
         atomicOr(&st->wait_timeout, 1u);
@@ -45,6 +47,7 @@ __device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* 
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   bool r = ok != 0;
@@ -175,69 +178,137 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
     for (int c = 0; c < NR; c++)
       if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * ldx] = v[c];
   }
-  __threadfence();
   __syncthreads();
-  if (tid == 0) __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  // one agent-scope release (L2 write-back) publishes every wave's stores
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// R = B - A X, A symmetric with its lower triangle stored.  Workgroup I owns
-// rows [64 I, 64 I + 64) and visits every column block J: A(I, J) for J < I,
-// the symmetric diagonal block, and A(J, I)^T for J > I.
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, int64_t lda,
-                                                  int64_t n, int nrhs,
-                                                  const double* __restrict__ X, int64_t ldx,
-                                                  const double* __restrict__ B, int64_t ldb,
-                                                  double* __restrict__ R, int64_t ldr) {
+// R = B - A X, A symmetric with its lower triangle stored, every stored
+// element read once (the diagonal tiles' lower halves twice).  Pass 1: workgroup (c, I) takes the lower tiles (I, J)
+// of row block I with J in chunk c ([RCH c, RCH c + RCH), J <= I); each
+// 64 x 64 tile is staged through LDS (the next one already loading into
+// registers) and used twice: A(I, J) x_J summed over the chunk into rowp,
+// and A(I, J)^T x_I (J < I) into colp of that tile.  Pass 2 adds, for row
+// block I, its chunk sums and the colp of the tiles (J', I), J' > I, in a
+// fixed order, and writes R = B - A X.
+constexpr int RCH = 8;
+
+__device__ inline int64_t tri_index(int64_t I, int64_t J) { return I * (I - 1) / 2 + J; }  // J < I
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_resid_part(const double* __restrict__ A, int64_t lda,
+                                                    int64_t n, int nrhs,
+                                                    const double* __restrict__ X, int64_t ldx,
+                                                    double* __restrict__ rowp,
+                                                    double* __restrict__ colp) {
   __shared__ double blk[NB][NB + 1];   // blk[q][r] = A_sym(64 I + r, 64 J + q)
-  __shared__ double xs[NB][MAXRHS];
-  __shared__ double acc[4][NB][MAXRHS];
+  __shared__ double xi[NB][NR], xj[NB][NR];
+  __shared__ double red[4][NB][NR];
   const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-  const int I = blockIdx.x;
+  const int64_t I = blockIdx.y;
+  const int64_t J0 = (int64_t)blockIdx.x * RCH;
+  if (J0 > I) return;                  // whole workgroup: no tile of this chunk is lower
+  const int64_t J1 = min(I + 1, J0 + RCH);
   const int nblk = (int)((n + NB - 1) / NB);
-  const int64_t i0 = (int64_t)I * NB;
+  const int nch = (nblk + RCH - 1) / RCH;
+  const int64_t i0 = I * NB;
   const int ni = (int)min((int64_t)NB, n - i0);
-  double part[MAXRHS];
-  for (int c = 0; c < MAXRHS; c++) part[c] = 0.0;
-  for (int J = 0; J < nblk; J++) {
-    const int64_t j0 = (int64_t)J * NB;
-    const int nj = (int)min((int64_t)NB, n - j0);
-    if (J < I) {
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        int i = idx & 63, q = idx >> 6;
-        blk[q][i] = (i < ni && q < nj) ? A[(i0 + i) + (j0 + q) * lda] : 0.0;
-      }
-    } else if (J > I) {
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        int q = idx & 63, i = idx >> 6;   // read A(j0 + q, i0 + i) down columns
-        blk[q][i] = (i < ni && q < nj) ? A[(j0 + q) + (i0 + i) * lda] : 0.0;
-      }
-    } else {
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        int i = idx & 63, q = idx >> 6;
-        double v = 0.0;
-        if (i < ni && q < nj) v = i >= q ? A[(i0 + i) + (j0 + q) * lda] : A[(j0 + q) + (i0 + i) * lda];
-        blk[q][i] = v;
-      }
-    }
-    for (int idx = tid; idx < NB * nrhs; idx += 256) {
-      int q = idx & 63, c = idx >> 6;
-      xs[q][c] = q < nj ? X[(j0 + q) + (int64_t)c * ldx] : 0.0;
-    }
-    __syncthreads();
-    for (int q = g; q < NB; q += 4) {
-      double a = blk[q][r];
-      for (int c = 0; c < nrhs; c++) part[c] += a * xs[q][c];
-    }
-    __syncthreads();
+  for (int idx = tid; idx < NB * NR; idx += 256) {
+    const int q = idx & 63, c = idx >> 6;
+    xi[q][c] = (q < ni && c < nrhs) ? X[(i0 + q) + (int64_t)c * ldx] : 0.0;
   }
-  for (int c = 0; c < nrhs; c++) acc[g][r][c] = part[c];
-  __syncthreads();
-  for (int idx = tid; idx < NB * nrhs; idx += 256) {
-    int i = idx & 63, c = idx >> 6;
-    if (i < ni) {
-      double t = (acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]);
-      R[(i0 + i) + (int64_t)c * ldr] = B[(i0 + i) + (int64_t)c * ldb] - t;
+  double rowacc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; c++) rowacc[c] = 0.0;
+  double tmp[NB * NB / 256];
+  auto fetch = [&](int64_t J) {
+    const int64_t j0 = J * NB;
+    const int nj = (int)min((int64_t)NB, n - j0);
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; u++) {
+      const int idx = tid + 256 * u;
+      const int i = min(idx & 63, ni - 1), q = min(idx >> 6, nj - 1);
+      // diagonal tile: the upper half is the mirror of the lower (never read)
+      const bool mirror = J == I && i < q;
+      const double v = mirror ? A[(i0 + q) + (j0 + i) * lda] : A[(i0 + i) + (j0 + q) * lda];
+      tmp[u] = ((idx & 63) < ni && (idx >> 6) < nj) ? v : 0.0;
     }
+  };
+  fetch(J0);
+  for (int64_t J = J0; J < J1; J++) {
+    const int64_t j0 = J * NB;
+    const int nj = (int)min((int64_t)NB, n - j0);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; u++) {
+      const int idx = tid + 256 * u;
+      blk[idx >> 6][idx & 63] = tmp[u];
+    }
+    for (int idx = tid; idx < NB * NR; idx += 256) {
+      const int q = idx & 63, c = idx >> 6;
+      xj[q][c] = (q < nj && c < nrhs) ? X[(j0 + q) + (int64_t)c * ldx] : 0.0;
+    }
+    if (J + 1 < J1) fetch(J + 1);
+    __syncthreads();
+    // rows of I: sum over q = g mod 4 of A_sym(r, q) x_J(q)
+    for (int q = g; q < NB; q += 4) {
+      const double a = blk[q][r];
+#pragma unroll
+      for (int c = 0; c < NR; c++) rowacc[c] += a * xj[q][c];
+    }
+    if (J < I) {
+      // rows of J: lane = q, sum over r = g mod 4 of A(r, q) x_I(r)
+      double z[NR];
+#pragma unroll
+      for (int c = 0; c < NR; c++) z[c] = 0.0;
+      const int q = r;
+      for (int rr = g; rr < NB; rr += 4) {
+        const double a = blk[q][rr];
+#pragma unroll
+        for (int c = 0; c < NR; c++) z[c] += a * xi[rr][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NR; c++) red[g][q][c] = z[c];
+      __syncthreads();
+      double* out = colp + tri_index(I, J) * NB * NR;
+      for (int idx = tid; idx < NB * NR; idx += 256) {
+        const int qq = idx % NB, c = idx / NB;
+        out[idx] = (red[0][qq][c] + red[1][qq][c]) + (red[2][qq][c] + red[3][qq][c]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NR; c++) red[g][r][c] = rowacc[c];
+  __syncthreads();
+  double* out = rowp + ((int64_t)I * nch + blockIdx.x) * NB * NR;
+  for (int idx = tid; idx < NB * NR; idx += 256) {
+    const int rr = idx % NB, c = idx / NB;
+    out[idx] = (red[0][rr][c] + red[1][rr][c]) + (red[2][rr][c] + red[3][rr][c]);
+  }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_resid_reduce(int64_t n, int nrhs,
+                                                      const double* __restrict__ rowp,
+                                                      const double* __restrict__ colp,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ R, int64_t ldr) {
+  const int64_t I = blockIdx.x;
+  const int nblk = (int)((n + NB - 1) / NB);
+  const int nch = (nblk + RCH - 1) / RCH;
+  const int64_t i0 = I * NB;
+  const int ni = (int)min((int64_t)NB, n - i0);
+  for (int idx = threadIdx.x; idx < NB * NR; idx += 256) {
+    const int rr = idx % NB, c = idx / NB;
+    if (rr >= ni || c >= nrhs) continue;
+    double t = 0.0;
+    for (int64_t ch = 0; ch * RCH <= I; ch++) t += rowp[((int64_t)I * nch + ch) * NB * NR + idx];
+    for (int64_t Jp = I + 1; Jp < nblk; Jp++) t += colp[tri_index(Jp, I) * NB * NR + idx];
+    R[(i0 + rr) + (int64_t)c * ldr] = B[(i0 + rr) + (int64_t)c * ldb] - t;
   }
 }
 
@@ -307,14 +378,40 @@ hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int 
   return hipGetLastError();
 }
 
+static int resid_nr(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
+
+size_t residual_work_bytes(int64_t n, int nrhs) {
+  if (n <= 0 || nrhs <= 0) return 0;
+  const int64_t nblk = (n + NB - 1) / NB, nch = (nblk + RCH - 1) / RCH;
+  const int64_t nr = resid_nr(nrhs);
+  return (size_t)(nblk * nch + nblk * (nblk - 1) / 2) * NB * nr * sizeof(double);
+}
+
+template <int NR>
+static void resid_launch(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
+                         int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
+                         double* work, hipStream_t s) {
+  const int64_t nblk = (n + NB - 1) / NB, nch = (nblk + RCH - 1) / RCH;
+  double* rowp = work;
+  double* colp = work + nblk * nch * NB * NR;
+  hipLaunchKernelGGL(k_resid_part<NR>, dim3((unsigned)nch, (unsigned)nblk), dim3(256), 0, s, A, lda,
+                     n, nrhs, X, ldx, rowp, colp);
+  hipLaunchKernelGGL(k_resid_reduce<NR>, dim3((unsigned)nblk), dim3(256), 0, s, n, nrhs, rowp, colp,
+                     B, ldb, R, ldr);
+}
+
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
-                           hipStream_t s) {
+                           double* work, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  if (nrhs > MAXRHS) return hipErrorInvalidValue;
-  int nblk = (int)((n + NB - 1) / NB);
-  hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(256), 0, s, A, lda, n, nrhs, X, ldx, B, ldb, R,
-                     ldr);
+  if (nrhs > MAXRHS || !work) return hipErrorInvalidValue;
+  switch (resid_nr(nrhs)) {
+    case 1: resid_launch<1>(A, lda, n, nrhs, X, ldx, B, ldb, R, ldr, work, s); break;
+    case 2: resid_launch<2>(A, lda, n, nrhs, X, ldx, B, ldb, R, ldr, work, s); break;
+    case 4: resid_launch<4>(A, lda, n, nrhs, X, ldx, B, ldb, R, ldr, work, s); break;
+    case 8: resid_launch<8>(A, lda, n, nrhs, X, ldx, B, ldb, R, ldr, work, s); break;
+    default: resid_launch<16>(A, lda, n, nrhs, X, ldx, B, ldb, R, ldr, work, s); break;
+  }
   return hipGetLastError();
 }
 

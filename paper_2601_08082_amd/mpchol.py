@@ -95,6 +95,7 @@ def _load() -> ct.CDLL:
     lib.mpchol_set_tune_table.argtypes = [vp, i32, ct.POINTER(CTuneEntry)]
     lib.mpchol_profile.argtypes = [vp, ct.c_uint32]
     lib.mpchol_profile_read.argtypes = [vp, ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(i64)]
+    lib.mpchol_backward_error.argtypes = [vp, i64, vp, i64, vp, i64, ct.POINTER(dbl), vp]
     lib.mpchol_policy_nodes.argtypes = [i64, ct.POINTER(CTree), ct.POINTER(i64)]
     lib.mpchol_policy_nodes.restype = i64
     lib.mpchol_policy_features.argtypes = [vp, i64, vp, i64, ct.POINTER(CTree), vp, vp]
@@ -289,6 +290,14 @@ class Context:
         if lib.mpchol_profile_read(self._h, ms, wk, nl) != 0:
             raise RuntimeError("mpchol_profile_read failed")
         return {k: (ms[i], wk[i], nl[i]) for i, k in enumerate(PROF_KINDS)}
+
+    def backward_error(self, A_cm, L_cm, n: int, stream=None):
+        """(||A - L L^T||_F / ||A||_F, ||A - L L^T||_F, ||A||_F) computed on the device."""
+        out = (ct.c_double * 2)()
+        r = lib.mpchol_backward_error(self._h, n, _ptr(A_cm), A_cm.shape[1], _ptr(L_cm),
+                                      L_cm.shape[1], out, _stream_handle(stream))
+        _raise(r, "mpchol_backward_error")
+        return (out[0] / out[1] if out[1] > 0 else 0.0), out[0], out[1]
 
     # ------------------------------------------------------------ learned policy
     def policy_features(self, A_cm, n: int, tree: Tree, stream=None):

@@ -123,7 +123,8 @@ def test_mlp_gradient_and_adam_vs_oracle(M, ctx, rows):
                              1, 1e-3)
     np.testing.assert_allclose(pd.cpu().numpy(), q, rtol=0, atol=2e-6)
     np.testing.assert_allclose(m.cpu().numpy(), mo, rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=1e-5, atol=1e-14)
+    # 1 - beta2 in FP32 is 1 - fl(0.999) = 0.00099998713 (relative 1.3e-5 from 0.001)
+    np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=3e-5, atol=1e-14)
 
 
 @pytest.fixture(scope="module")
@@ -177,12 +178,15 @@ def _cost(M, n, tree):
 @pytest.mark.parametrize("ratio", [1.05, 8.0])
 def test_policy_gain(M, ctx, trained, ratio):
     """The learned tree solves to 1e-12 like the fixed trees, at a fraction of
-    the all-FP64 tree's modelled MFMA time, and with a backward error inside
-    the error budget where the fixed all-FP16 tree is outside it (weakly
-    dominant matrix) or at lower modelled cost (strongly dominant matrix)."""
+    the all-FP64 tree's modelled MFMA time, and is the cheapest tree whose
+    error bound (the sum over nodes of the label error e_k of the node's
+    chosen format) stays inside the budget tau: on a strongly dominant matrix
+    it takes FP8 where the fixed tree takes FP16 (lower modelled cost); on a
+    weakly dominant one it keeps FP16 where an all-FP8 tree's bound exceeds
+    the budget."""
     from paper_2601_08082_amd import spdgen_gpu
     P = trained["P"]
-    n = 1536
+    n, tau = 1536, 1e-4
     A = spdgen_gpu.gen_spd(n, ratio, 0.0, seed=99)
     B = spdgen_gpu.gen_rhs(n, 1, seed=199)
     X, info = P.solve_with_policy(ctx, A, B, n, trained["params"], tree=trained["tree"])
@@ -192,13 +196,23 @@ def test_policy_gain(M, ctx, trained, ratio):
     x = M.from_device_cm(X)[:n]
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-12
     t = trained["tree"]
-    learned = M.Tree(leaf=t.leaf, offdiag=[M.F16], scale_mode=1, node_prec=info["node_prec"])
+    choice = np.array(info["node_prec"])
+    learned = M.Tree(leaf=t.leaf, offdiag=[M.F16], scale_mode=1, node_prec=list(choice))
     f16 = M.Tree(leaf=t.leaf, offdiag=[M.F16], scale_mode=1)
     f64 = M.Tree(leaf=t.leaf, offdiag=[M.F64])
     c_l, c_16, c_64 = _cost(M, n, learned), _cost(M, n, f16), _cost(M, n, f64)
-    assert c_l <= 0.5 * c_64
+    # error bounds from the oracle's node errors (FP64 factor of the same A)
+    L64 = O.factor(Ah, tree=O.Tree(leaf=t.leaf, offdiag=[O.F64]))[0]
+    e = OP.node_errors(Ah, L64, n, t.leaf, 1, scale_mode=1)
+    e4 = np.concatenate([e, np.zeros((e.shape[0], 1))], axis=1)   # F64: no quantization error
+    bound_l = float(np.sum(e4[np.arange(len(choice)), choice]))
+    bound_e4m3 = float(np.sum(e[:, O.E4M3]))
     be_l = O.backward_error(Ah, M.from_device_cm(ctx.factor(A, n, learned)[0]))
-    be_16 = O.backward_error(Ah, M.from_device_cm(ctx.factor(A, n, f16)[0]))
-    print(f"[gpu] policy gain ratio {ratio}: choice {info['node_prec']} cost learned/f16/f64 "
-          f"{c_l:.3e}/{c_16:.3e}/{c_64:.3e} be learned/f16 {be_l:.2e}/{be_16:.2e}", flush=True)
-    assert (be_l < be_16 and be_l <= 1e-4) or c_l < c_16
+    print(f"[gpu] policy gain ratio {ratio}: choice {choice.tolist()} cost learned/f16/f64 "
+          f"{c_l:.3e}/{c_16:.3e}/{c_64:.3e} bound learned {bound_l:.2e} all-e4m3 {bound_e4m3:.2e} "
+          f"backward error {be_l:.2e}", flush=True)
+    assert c_l <= 0.5 * c_64 and bound_l <= tau and be_l <= tau
+    if ratio > 4:
+        assert c_l < c_16
+    else:
+        assert bound_e4m3 > tau and c_l <= c_16
