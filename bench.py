@@ -31,7 +31,8 @@ PEAKS = {"gemm_e4m3": (5000.0, "TFLOP/s", "mfma"), "gemm_f16": (2500.0, "TFLOP/s
          "gemm_f32": (157.3, "TFLOP/s", "mfma"), "gemm_f64": (78.6, "TFLOP/s", "mfma"),
          "potrf": (78.6, "TFLOP/s", "alu"), "trsm": (78.6, "TFLOP/s", "alu"),
          "cast": (8000.0, "GB/s", "hbm"), "maxabs": (8000.0, "GB/s", "hbm"),
-         "trsv": (8000.0, "GB/s", "hbm"), "residual": (8000.0, "GB/s", "hbm")}
+         "trsv": (8000.0, "GB/s", "hbm"), "residual": (8000.0, "GB/s", "hbm"),
+         "trinv": (78.6, "TFLOP/s", "alu")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f16_n16384_pmc.md")
 GEMM_SRC = [os.path.join(ROOT, "paper_2601_08082_amd", "csrc", f) for f in ("k_gemm.hip", "dev_gemm.h")]
 

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define MPCHOL_ABI_VERSION 1
+#define MPCHOL_ABI_VERSION 2
 #define MPCHOL_MAX_LEVELS 24
 
 /* Operand precisions.  E4M3 is the OCP 8-bit e4m3fn format (max 448). */
@@ -73,6 +73,11 @@ enum {
  *                up to a power of two); 1: also scale up (e < 0) for FP16 and
  *                E4M3 operands.  FP32 operands are never scaled up.
  *   scale_tile   must be 0 (one scale per GEMM operand block).
+ *   leaf_trsm    0: an FP64 leaf TRSM (Algorithm 2 base case) multiplies by
+ *                the leaf's inverse, formed once per kernel leaf (FP64 MFMA,
+ *                no dependency chain along the columns; equal up to rounding);
+ *                1: column substitution with correctly rounded quotients (the
+ *                bit-exact reference).  FP32 leaves always substitute.
  *   node_prec    NULL, or a HOST array of n_nodes int8 precisions, one per
  *                internal Tree-POTRF node in preorder (node, then its A11
  *                subtree, then its A22 subtree); entries < 0 fall back to
@@ -88,6 +93,7 @@ typedef struct {
   int32_t syrk_leaf_mode;
   int32_t scale_mode;
   int32_t scale_tile;
+  int32_t leaf_trsm;
   const int8_t* node_prec;
   int64_t n_nodes;
 } mpchol_tree;
@@ -216,7 +222,8 @@ enum {
   MPCHOL_PROF_TRSM = 7,       /* leaf TRSM                 */
   MPCHOL_PROF_TRSV = 8,       /* triangular solves of mpchol_solve (work: bytes of L read) */
   MPCHOL_PROF_RESIDUAL = 9,   /* FP64 residuals of mpchol_solve (work: bytes of A read)    */
-  MPCHOL_PROF_KINDS = 10
+  MPCHOL_PROF_TRINV = 10,     /* FP64 leaf inverses (work: m^3/3 flops)    */
+  MPCHOL_PROF_KINDS = 11
 };
 /* mpchol_profile: clear the accumulators and record a HIP event pair around
  * every later launch whose class bit is set in kind_mask (0 = off).  Events go

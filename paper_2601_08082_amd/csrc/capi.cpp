@@ -37,6 +37,8 @@ struct mpchol_ctx_s {
   DevStatus* hst = nullptr;   // pinned host copy
   void* ws = nullptr;         // quantized operand copies
   size_t ws_bytes = 0;
+  double* inv = nullptr;      // FP64 leaf inverses (KL x KL per slot)
+  int ninv = 0;
   double* part = nullptr;     // max-abs partials
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
@@ -93,6 +95,7 @@ static int launch_kind(const Launch& L) {
     case Launch::CAST: return MPCHOL_PROF_CAST;
     case Launch::MAXABS: return MPCHOL_PROF_MAXABS;
     case Launch::POTRF: return MPCHOL_PROF_POTRF;
+    case Launch::TRINV: return MPCHOL_PROF_TRINV;
     default: return MPCHOL_PROF_TRSM;
   }
 }
@@ -153,7 +156,7 @@ static double launch_work(const Plan& P, const Launch& L) {
       const MaxabsJob& j = P.maxabs[L.first + i];
       w += (double)j.rows * j.cols * 8.0;
     }
-  } else if (L.kind == Launch::POTRF) {
+  } else if (L.kind == Launch::POTRF || L.kind == Launch::TRINV) {
     w = (double)L.a1 * L.a1 * L.a1 / 3.0;
   } else {
     w = (double)L.a1 * L.a3 * L.a3;
@@ -225,7 +228,15 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
         e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, s);
         break;
       case Launch::TRSM:
-        e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
+        if (Lc.first >= 0)
+          e = launch_trsm_inv(L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3,
+                              c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
+        else
+          e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
+        break;
+      case Launch::TRINV:
+        e = launch_trinv(L, ldl, Lc.a0, (int)Lc.a1,
+                         c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
         break;
       case Launch::MAXABS:
         e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
@@ -548,6 +559,7 @@ int mpchol_destroy(mpchol_ctx c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c->plans) free_plan(*kv.second);
   if (c->ws) (void)hipFree(c->ws);
+  if (c->inv) (void)hipFree(c->inv);
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
   if (c->resw) (void)hipFree(c->resw);
@@ -585,6 +597,14 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
   if (r) return r;
   r = ensure_ws(c, std::max<size_t>(P->ws_bytes, 256), std::max<int64_t>(P->parts, 1));
   if (r) return r;
+  if (P->ninv > c->ninv) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->inv) HIPCHK(hipFree(c->inv));
+    c->inv = nullptr;
+    c->ninv = 0;
+    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kKernelLeaf * kKernelLeaf * (size_t)P->ninv));
+    c->ninv = P->ninv;
+  }
   if (info) HIPCHK(hipEventRecord(c->ev0, s));
   HIPCHK(launch_status_init(c->dst, s));
   if (L != A) HIPCHK(launch_copy_lower(A, lda, L, ldl, n, s));
@@ -813,6 +833,10 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         build_plan(P, n_host[i], ldl_host[i], &t, true, tile);
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
+          if (L.kind == Launch::TRINV || (L.kind == Launch::TRSM && L.first >= 0)) {
+            free_batch(c);
+            return MPCHOL_HIP_ERROR;   // workgroup-level plans never use leaf inverses
+          }
           BatchTask T{};
           T.kind = (int32_t)L.kind;
           T.prec = L.prec;

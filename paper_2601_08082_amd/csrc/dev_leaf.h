@@ -271,4 +271,164 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
   }
 }
 
+// ---------------------------------------------------------------- inverse
+// Y = L^{-1} of the FP64 leaf L = A(i0:i0+m, i0:i0+m), m <= 128, into Y
+// (column-major, ld KL, zero above the diagonal and outside m x m).  L and Y
+// live in LDS as 16 x 16 lower blocks (row-major, padded rows).  Diagonal
+// blocks: column-by-column substitution with true division; off-diagonal
+// blocks by block columns, Y_ij = -Y_ii (sum_{k=j}^{i-1} L_ik Y_kj), with
+// FP64 MFMA (the partial sum stays in the accumulator, whose register layout
+// is exactly the B-operand layout of the next product).
+constexpr int IB = 16, IBP = 17, NIB = KL / IB;             // 8 x 8 blocks
+constexpr int inv_blocks() { return NIB * (NIB + 1) / 2; }  // lower blocks
+constexpr int trinv_lds_bytes() { return 2 * inv_blocks() * IB * IBP * 8; }
+
+__device__ inline int iblk(int i, int j) { return (i * (i + 1) / 2 + j) * IB * IBP; }  // i >= j
+
+__device__ inline void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, int64_t i0, int m,
+                                  double* __restrict__ Y, char* lds) {
+  double* l = reinterpret_cast<double*>(lds);   // L blocks
+  double* y = l + inv_blocks() * IB * IBP;      // Y blocks
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = (m + IB - 1) / IB;
+  const double* A = Lm + i0 + i0 * ldl;
+  {
+    double v[KL * KL / 256];
+#pragma unroll
+    for (int r = 0; r < KL * KL / 256; r++) {
+      const int idx = tid + 256 * r;
+      const int i = idx % KL, j = idx / KL;
+      v[r] = A[min(i, m - 1) + (int64_t)min(j, m - 1) * ldl];
+    }
+#pragma unroll
+    for (int r = 0; r < KL * KL / 256; r++) {
+      const int idx = tid + 256 * r;
+      const int i = idx % KL, j = idx / KL;
+      if ((i >> 4) >= (j >> 4) && (i >> 4) < nb)
+        l[iblk(i >> 4, j >> 4) + (i & 15) * IBP + (j & 15)] =
+            (i < m && j < m) ? (i >= j ? v[r] : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  // diagonal blocks: thread = (block, column c); y_r for r >= c
+  if (tid < nb * IB) {
+    const int bb = tid >> 4, c = tid & 15;
+    const double* L = l + iblk(bb, bb);
+    double x[IB];
+#pragma unroll
+    for (int r = 0; r < IB; r++) {
+      double s = r == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < r; k++)
+        if (k >= c) s = s - L[r * IBP + k] * x[k];
+      x[r] = r < c ? 0.0 : s / L[r * IBP + r];
+    }
+    double* Yd = y + iblk(bb, bb);
+#pragma unroll
+    for (int r = 0; r < IB; r++) Yd[r * IBP + c] = x[r];
+  }
+  __syncthreads();
+  // off-diagonal blocks: wave w takes block columns w and 7 - w
+  for (int h = 0; h < 2; h++) {
+    const int j = h == 0 ? wave : NIB - 1 - wave;
+    if (j >= nb) continue;
+    for (int i = j + 1; i < nb; i++) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = j; k < i; k++) {
+        const double* Lik = l + iblk(i, k);
+        const double* Ykj = y + iblk(k, j);
+#pragma unroll
+        for (int q0 = 0; q0 < IB; q0 += 4) {
+          const double av = Lik[(lane & 15) * IBP + q0 + (lane >> 4)];   // A(row, kk)
+          const double bv = Ykj[(q0 + (lane >> 4)) * IBP + (lane & 15)]; // B(kk, col)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+      }
+      // acc[r] holds S(lane/16 + 4r, lane%16): the B operand for k-chunk 4r
+      const double* Yii = y + iblk(i, i);
+      f64x4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const double av = Yii[(lane & 15) * IBP + 4 * r + (lane >> 4)];
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(av, acc[r], t, 0, 0, 0);
+      }
+      double* Yij = y + iblk(i, j);
+#pragma unroll
+      for (int r = 0; r < 4; r++) Yij[((lane >> 4) + 4 * r) * IBP + (lane & 15)] = -t[r];
+      wave_lds_order();
+    }
+  }
+  __syncthreads();
+#pragma unroll 8
+  for (int r = 0; r < KL * KL / 256; r++) {
+    const int idx = tid + 256 * r;
+    const int i = idx % KL, j = idx / KL;   // Y(i, j), column-major, ld KL
+    double v = 0.0;
+    if (i < m && j < m && i >= j) v = y[iblk(i >> 4, j >> 4) + (i & 15) * IBP + (j & 15)];
+    Y[i + j * KL] = v;
+  }
+}
+
+// Rows [r0 + 16 rblk, +16) of B <- B L^{-T} = B Y^T with Y = L^{-1} from
+// trinv_body: X(i, j) = sum_{l <= j} B(i, l) Y(j, l), FP64 MFMA.  Wave w
+// computes column blocks w and 7 - w; every wave reads the whole row block of
+// B before any wave writes (in place).
+__device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64_t r0, int64_t m,
+                                     int64_t c0, int k, const double* __restrict__ Y, int rblk) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t rb = r0 + (int64_t)rblk * IB;
+  const int rows = (int)min((int64_t)IB, r0 + m - rb);
+  const int nb = (k + IB - 1) / IB;
+  double* B = Lm + rb + c0 * ldl;
+  const int cbs[2] = {wave, NIB - 1 - wave};
+  const int lbmax = max(cbs[0] < nb ? cbs[0] : -1, cbs[1] < nb ? cbs[1] : -1);
+  // A fragments: a[lb][q] = B(lane%16, 16 lb + 4 q + lane/16)
+  double a[NIB][4];
+  const int ri = min(lane & 15, rows - 1);
+#pragma unroll
+  for (int lb = 0; lb < NIB; lb++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int col = 16 * lb + 4 * q + (lane >> 4);
+      const double v = B[ri + (int64_t)min(col, k - 1) * ldl];
+      a[lb][q] = (lb <= lbmax && col < k && (lane & 15) < rows) ? v : 0.0;
+    }
+  f64x4 acc[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int cb = cbs[h];
+    if (cb >= nb) continue;
+#pragma unroll
+    for (int lb = 0; lb < NIB; lb++) {
+      if (lb > cb) break;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        // B operand (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk)
+        const double bv = Y[(16 * cb + (lane & 15)) + (16 * lb + 4 * q + (lane >> 4)) * KL];
+        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], bv, acc[h], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();   // every wave has consumed its reads of B
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int cb = cbs[h];
+    if (cb >= nb) continue;
+    const int col = 16 * cb + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = (lane >> 4) + 4 * r;
+      if (row < rows && col < k) B[row + (int64_t)col * ldl] = acc[h][r];
+    }
+  }
+}
+
 }  // namespace mpc

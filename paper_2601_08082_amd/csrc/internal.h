@@ -77,6 +77,11 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
                        int scale_mode, DevStatus* st, hipStream_t s);
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m,
                              DevStatus* st, hipStream_t s);
+// FP64 leaf inverse (Y: KL x KL, column-major, ld KL) and the TRSM through it.
+hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y,
+                        hipStream_t s);
+hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
+                           const double* Y, hipStream_t s);
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,
                             int64_t c0, int k, hipStream_t s);
 

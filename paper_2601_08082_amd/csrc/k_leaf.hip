@@ -16,6 +16,13 @@
 // which equals the correctly rounded a / b (Markstein 1990) barring
 // overflow/underflow, with three dependent operations instead of a full
 // division on the elimination chain.
+//
+// FP64 leaves can instead be solved through their inverse: k_trinv forms
+// Y = L^{-1} once per leaf (block substitution, FP64 MFMA for the
+// off-diagonal blocks) and k_trsm_inv computes B <- B Y^T as an FP64 MFMA
+// product, 16 rows per workgroup, with no dependency chain along the
+// columns.  Same values up to rounding; the substitution kernel remains the
+// bit-exact reference mode.
 #include "dev_leaf.h"
 
 namespace mpc {
@@ -32,6 +39,35 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(double* __restrict__ Lm, int6
                                                    int64_t r0, int64_t m, int64_t c0, int k) {
   __shared__ __attribute__((aligned(16))) char pool[trsm_leaf_lds_bytes<T>()];
   trsm_leaf_rows<T>(Lm, ldl, r0, m, c0, k, blockIdx.x, pool);
+}
+
+__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Lm, int64_t ldl,
+                                               int64_t i0, int m, double* __restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) char pool[trinv_lds_bytes()];
+  trinv_body(Lm, ldl, i0, m, Y, pool);
+}
+
+__global__ __launch_bounds__(256) void k_trsm_inv(double* __restrict__ Lm, int64_t ldl, int64_t r0,
+                                                  int64_t m, int64_t c0, int k,
+                                                  const double* __restrict__ Y) {
+  trsm_inv_rows(Lm, ldl, r0, m, c0, k, Y, blockIdx.x);
+}
+
+hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y,
+                        hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (m > KL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trinv, dim3(1), dim3(256), 0, s, Lm, ldl, i0, m, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
+                           const double* Y, hipStream_t s) {
+  if (m <= 0 || k <= 0) return hipSuccess;
+  if (k > KL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trsm_inv, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, Lm, ldl, r0, m,
+                     c0, k, Y);
+  return hipGetLastError();
 }
 
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m, DevStatus* st,

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <sstream>
 
 namespace mpc {
@@ -46,6 +47,7 @@ int validate_tree(const mpchol_tree* t) {
   if (t->syrk_leaf_mode < 0 || t->syrk_leaf_mode > 1) return -7;
   if (t->scale_mode < 0 || t->scale_mode > 1) return -7;
   if (t->scale_tile != 0) return MPCHOL_NOT_SUPPORTED;
+  if (t->leaf_trsm != 0 && t->leaf_trsm != 1) return -7;
   if (t->n_nodes < 0 || (t->n_nodes > 0 && !t->node_prec)) return -7;
   for (int64_t i = 0; i < t->n_nodes; i++)
     if (t->node_prec[i] > MPCHOL_F64) return -7;
@@ -55,7 +57,7 @@ int validate_tree(const mpchol_tree* t) {
 std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t) {
   std::ostringstream o;
   o << n << ':' << ldl << ':' << t->leaf << ':' << t->split_align << ':' << t->leaf_prec << ':'
-    << t->syrk_leaf_mode << ':' << t->scale_mode << ':';
+    << t->syrk_leaf_mode << ':' << t->scale_mode << ':' << t->leaf_trsm << ':';
   for (int i = 0; i < t->nlevels; i++) o << t->offdiag[i] << ',';
   o << ':';
   for (int64_t i = 0; i < t->n_nodes; i++) o << (int)t->node_prec[i] << ',';
@@ -72,6 +74,10 @@ struct Builder {
   int64_t ldl;
   bool single_wg = false;
   int tile_force = 0;
+  std::map<int64_t, std::pair<int, int64_t>> inv_slot;   // kernel-leaf origin -> (slot, order)
+
+  // FP64 leaves of the single-matrix path solve their TRSMs through the inverse
+  bool use_inverse() const { return !single_wg && t.leaf_prec == F64 && t.leaf_trsm == 0; }
   int64_t next_node = 0;
   size_t ws_cursor = 0;   // bytes used by the current group of quantized copies
   int64_t part_cursor = 0;
@@ -216,12 +222,14 @@ struct Builder {
       Launch L{Launch::GEMM, prec};
       L.first = (int)P.gemms.size();
       L.count = (int)gp.size();
-      // 128 x 128 tiles unless that leaves most of the 256 CUs idle
-      int64_t t128 = 0;
-      for (auto& g : gp) {
-        int64_t tm = cdiv(g.m, 128);
-        t128 += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, 128);
-      }
+      auto tiles_of = [&](int T) {
+        int64_t tot = 0;
+        for (auto& g : gp) {
+          int64_t tm = cdiv(g.m, T);
+          tot += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, T);
+        }
+        return tot;
+      };
       if (tile_force) {
         L.tile = tile_force;
       } else if (single_wg) {
@@ -229,7 +237,17 @@ struct Builder {
         for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
         L.tile = mn >= 128 ? 128 : 64;
       } else {
+        // 128 x 128 tiles unless that leaves most of the 256 CUs idle; FP16 /
+        // E4M3 groups move to 256 x 256 tiles (4x the fragment reuse per LDS
+        // read) when the rounds of 256 workgroups, weighted by tile area over
+        // the shape's relative MFMA efficiency, come out cheaper
+        const int64_t t128 = tiles_of(128);
         L.tile = t128 >= 256 ? 128 : 64;
+        if ((prec == F16 || prec == E4M3) && L.tile == 128) {
+          const double c128 = (double)cdiv(t128, 256) * 128.0 * 128.0 / 0.30;
+          const double c256 = (double)cdiv(tiles_of(256), 256) * 256.0 * 256.0 / 0.55;
+          if (c256 < c128) L.tile = 256;
+        }
       }
       int tiles = 0;
       for (auto& g : gp) {
@@ -261,6 +279,14 @@ struct Builder {
       L.a1 = m;
       P.launches.push_back(L);
       P.stats.leaf_flops += (double)m * m * m / 3.0;
+      if (use_inverse()) {
+        Launch I{Launch::TRINV, F64};
+        I.a0 = i0;
+        I.a1 = m;
+        I.first = P.ninv++;
+        inv_slot[i0] = {I.first, m};
+        P.launches.push_back(I);
+      }
       return;
     }
     int64_t m1 = leaf_split(m), m2 = m - m1;
@@ -280,6 +306,9 @@ struct Builder {
       L.a1 = m;
       L.a2 = c0;
       L.a3 = k;
+      L.first = -1;
+      auto it = inv_slot.find(c0);
+      if (use_inverse() && it != inv_slot.end() && it->second.second == k) L.first = it->second.first;
       P.launches.push_back(L);
       P.stats.leaf_flops += (double)m * k * k;
       return;

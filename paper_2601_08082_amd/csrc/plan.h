@@ -12,11 +12,12 @@
 namespace mpc {
 
 struct Launch {
-  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM } kind;
+  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV } kind;
   int prec;
-  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF: i0, m; TRSM: r0, m, c0, k
-  int first = 0, count = 0, total = 0;    // descriptor range, workgroups
-  int tile = 128;                         // GEMM output tile (64 or 128)
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k
+  int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM:
+                                          // leaf-inverse slot (TRSM: -1 = substitution)
+  int tile = 128;                         // GEMM output tile (64, 128; 256 for FP16 / E4M3)
 };
 
 struct PlanStats {
@@ -36,6 +37,7 @@ struct Plan {
   std::vector<GemmProb> gemms;
   size_t ws_bytes = 0;     // quantized-operand workspace needed
   int64_t parts = 0;       // maxabs partial slots needed
+  int ninv = 0;            // leaf-inverse slots (KL x KL doubles each)
   PlanStats stats;
   // device copies of the descriptor arrays
   MaxabsJob* d_maxabs = nullptr;

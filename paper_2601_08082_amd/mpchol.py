@@ -24,8 +24,8 @@ import numpy as np
 E4M3, F16, F32, F64 = 0, 1, 2, 3
 OK, NOT_SPD, NONFINITE, NOT_CONVERGED, HIP_ERROR, NOT_SUPPORTED = 0, 1, 2, 3, 4, 5
 PROF_KINDS = ["gemm_e4m3", "gemm_f16", "gemm_f32", "gemm_f64", "cast", "maxabs", "potrf", "trsm",
-              "trsv", "residual"]
-ABI_VERSION = 1
+              "trsv", "residual", "trinv"]
+ABI_VERSION = 2
 MAX_LEVELS = 24
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +43,7 @@ class CTree(ct.Structure):
         ("syrk_leaf_mode", ct.c_int32),
         ("scale_mode", ct.c_int32),
         ("scale_tile", ct.c_int32),
+        ("leaf_trsm", ct.c_int32),
         ("node_prec", ct.POINTER(ct.c_int8)),
         ("n_nodes", ct.c_int64),
     ]
@@ -123,6 +124,7 @@ class Tree:
     syrk_leaf_mode: int = 0
     scale_mode: int = 0
     node_prec: Optional[Sequence[int]] = None
+    leaf_trsm: int = 0          # 0: FP64 leaf TRSM through the leaf inverse; 1: substitution
 
     def to_c(self):
         t = CTree()
@@ -136,6 +138,7 @@ class Tree:
         t.syrk_leaf_mode = self.syrk_leaf_mode
         t.scale_mode = self.scale_mode
         t.scale_tile = 0
+        t.leaf_trsm = self.leaf_trsm
         keep = None
         if self.node_prec is not None and len(self.node_prec):
             keep = (ct.c_int8 * len(self.node_prec))(*self.node_prec)

@@ -79,11 +79,53 @@ def _trees(M):
 @pytest.mark.parametrize("n", [1, 7, 64, 130, 300])
 @pytest.mark.parametrize("ti", range(8))
 def test_integer_factor_bitwise(M, ctx, n, ti):
+    """Substitution leaf TRSM: L0 bit for bit.  Inverse-based leaf TRSM (the
+    default for FP64 leaves): L0 up to the rounding of the leaf inverses."""
+    import dataclasses
     print(f"[gpu] integer L0 n={n} tree={ti}", flush=True)
     L0, A = _integer_L0(n, seed=1000 + n + ti)
-    L, info = _gpu_factor(M, ctx, A, n, _trees(M)[ti])
+    t = _trees(M)[ti]
+    L, info = _gpu_factor(M, ctx, A, n, dataclasses.replace(t, leaf_trsm=1))
     assert info["status"] == M.OK, info
     np.testing.assert_array_equal(np.tril(L[:n, :n]), L0)
+    L, info = _gpu_factor(M, ctx, A, n, dataclasses.replace(t, leaf_trsm=0))
+    assert info["status"] == M.OK, info
+    assert np.max(np.abs(np.tril(L[:n, :n]) - L0)) <= 1e-13 * np.max(np.abs(L0))
+
+
+@pytest.mark.parametrize("n,leaf", [(5, 4), (100, 37), (300, 64), (700, 128), (1111, 200)])
+def test_leaf_inverse_trsm_vs_substitution(M, ctx, n, leaf):
+    """The two leaf-TRSM modes agree to FP64 rounding on ragged leaves."""
+    import dataclasses
+    print(f"[gpu] leaf inverse vs substitution n={n} leaf={leaf}", flush=True)
+    A = spdgen.gen_spd(n, 1.1, 0.0, seed=n + 5)
+    t = M.Tree(leaf=leaf, offdiag=[M.F64])
+    Ls, _ = _gpu_factor(M, ctx, A, n, dataclasses.replace(t, leaf_trsm=1))
+    Li, info = _gpu_factor(M, ctx, A, n, t)
+    assert info["status"] == M.OK
+    assert np.linalg.norm(np.tril(Li[:n, :n] - Ls[:n, :n])) <= 1e-14 * np.linalg.norm(np.tril(Ls[:n, :n]))
+
+
+@pytest.mark.parametrize("prec", ["F16", "E4M3"])
+def test_integer_factor_bitwise_large_tiles(M, ctx, prec):
+    """n = 8192 with leaf 256: the level-0 SYRK runs on 256 x 256 MFMA tiles
+    (the 128-tile grid would need three rounds of the chip).  A = L0 L0^T is
+    formed on the device in FP64 (exact: entries < 2^53)."""
+    import torch
+    n = 8192
+    print(f"[gpu] integer L0 n={n} {prec} (256 tiles)", flush=True)
+    g = torch.Generator(device="cpu").manual_seed(77)
+    L0 = torch.tril(torch.randint(-3, 4, (n, n), generator=g), -1).to(torch.float64)
+    L0 += torch.diag(torch.randint(n // 2, n + 1, (n,), generator=g).to(torch.float64))
+    L0d = L0.cuda()
+    # column-major storage of A = L0 L0^T is the row-major storage of A^T = A
+    A = (L0d @ L0d.T.contiguous()).contiguous()
+    t = M.Tree(leaf=256, offdiag=[getattr(M, prec)], scale_mode=1 if prec == "E4M3" else 0,
+               leaf_trsm=1)
+    L, info = ctx.factor(A, n, t)
+    assert info["status"] == M.OK, info
+    # L is column-major: its (n, ld) tensor holds L^T row-major
+    assert torch.equal(torch.tril(L.T), L0d)
 
 
 def _tridiag(n, c, d):
@@ -98,8 +140,9 @@ def _tridiag(n, c, d):
 def test_tridiagonal_bitwise_vs_oracle(M, ctx, ti):
     print(f"[gpu] tridiagonal tree={ti}", flush=True)
     n = 333
+    import dataclasses
     A = _tridiag(n, -1.0, 2.5)
-    t = _trees(M)[ti]
+    t = dataclasses.replace(_trees(M)[ti], leaf_trsm=1)
     L, info = _gpu_factor(M, ctx, A, n, t)
     Lo, st, _ = O.factor(A, tree=_otree(M, t))
     assert info["status"] == M.OK and st == O.OK
