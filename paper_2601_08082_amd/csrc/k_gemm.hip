@@ -6,7 +6,7 @@
 // with FP32 accumulation for FP16 / E4M3 / FP32 operands and FP64 for FP64
 // (Section 3.3 layering; Section 3.4 dequantization by the block scales).
 // One launch handles a list of independent problems; every workgroup owns one
-// output tile (64 or 128 square; 256 for FP16 / E4M3 operands) of one problem.  The bodies live in
+// output tile (64 or 128 square) of one problem.  The bodies live in
 // dev_gemm.h.
 //
 // Output orientation: the MFMA computes D = Y X^T so that the lane index runs
@@ -69,13 +69,6 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
     launch_gemm_bm<64>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
   } else if (tile == 128) {
     launch_gemm_bm<128>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
-  } else if (tile == 256 && prec == F16) {
-    // 256 x 256 tiles (4 x 4 MFMA blocks per wave) for the quantized operands only
-    hipLaunchKernelGGL((k_gemm_q<_Float16, 256>), g, b, 0, s, Lm, ldl, (const _Float16*)ws, probs,
-                       nprobs, part, prec, scale_mode, st);
-  } else if (tile == 256 && prec == E4M3) {
-    hipLaunchKernelGGL((k_gemm_q<unsigned char, 256>), g, b, 0, s, Lm, ldl,
-                       (const unsigned char*)ws, probs, nprobs, part, prec, scale_mode, st);
   } else {
     return hipErrorInvalidValue;
   }

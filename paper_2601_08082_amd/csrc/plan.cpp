@@ -237,17 +237,10 @@ struct Builder {
         for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
         L.tile = mn >= 128 ? 128 : 64;
       } else {
-        // 128 x 128 tiles unless that leaves most of the 256 CUs idle; FP16 /
-        // E4M3 groups move to 256 x 256 tiles (4x the fragment reuse per LDS
-        // read) when the rounds of 256 workgroups, weighted by tile area over
-        // the shape's relative MFMA efficiency, come out cheaper
-        const int64_t t128 = tiles_of(128);
-        L.tile = t128 >= 256 ? 128 : 64;
-        if ((prec == F16 || prec == E4M3) && L.tile == 128) {
-          const double c128 = (double)cdiv(t128, 256) * 128.0 * 128.0 / 0.30;
-          const double c256 = (double)cdiv(tiles_of(256), 256) * 256.0 * 256.0 / 0.55;
-          if (c256 < c128) L.tile = 256;
-        }
+        // 128 x 128 tiles unless that leaves most of the 256 CUs idle (256 x
+        // 256 tiles of this kernel measured slower at every level-0 shape:
+        // one workgroup per CU cannot hide the load latency)
+        L.tile = tiles_of(128) >= 256 ? 128 : 64;
       }
       int tiles = 0;
       for (auto& g : gp) {

@@ -17,7 +17,7 @@ struct Launch {
   int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k
   int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM:
                                           // leaf-inverse slot (TRSM: -1 = substitution)
-  int tile = 128;                         // GEMM output tile (64, 128; 256 for FP16 / E4M3)
+  int tile = 128;                         // GEMM output tile (64 or 128)
 };
 
 struct PlanStats {

@@ -108,12 +108,12 @@ def test_leaf_inverse_trsm_vs_substitution(M, ctx, n, leaf):
 
 @pytest.mark.parametrize("prec", ["F16", "E4M3"])
 def test_integer_factor_bitwise_large_tiles(M, ctx, prec):
-    """n = 8192 with leaf 256: the level-0 SYRK runs on 256 x 256 MFMA tiles
-    (the 128-tile grid would need three rounds of the chip).  A = L0 L0^T is
-    formed on the device in FP64 (exact: entries < 2^53)."""
+    """n = 8192 with leaf 256: multi-round grids of 128 x 128 MFMA tiles and
+    K up to 4096 in the FP32 accumulators (sums stay below 2^24).  A = L0 L0^T
+    is formed on the device in FP64 (exact: entries < 2^53)."""
     import torch
     n = 8192
-    print(f"[gpu] integer L0 n={n} {prec} (256 tiles)", flush=True)
+    print(f"[gpu] integer L0 n={n} {prec}", flush=True)
     g = torch.Generator(device="cpu").manual_seed(77)
     L0 = torch.tril(torch.randint(-3, 4, (n, n), generator=g), -1).to(torch.float64)
     L0 += torch.diag(torch.randint(n // 2, n + 1, (n,), generator=g).to(torch.float64))
