@@ -161,6 +161,54 @@ def solve_with_policy(ctx, A, B, n: int, params, tree=None, tol: float = 1e-13,
     raise RuntimeError("every tree of the fallback chain failed")
 
 
+def evaluate(ctx, params, n: int = 32768, ratio: float = 1.1, leaf: int = 256, reps: int = 3,
+             seed: int = 55):
+    """Time to a refined solution (1e-13 correction) of one seeded system
+    with the learned tree, the fixed all-FP16 tree and the all-FP64 tree;
+    the learned tree's fallbacks counted.  Times are medians over `reps`
+    after one warm-up, inputs resident on the device."""
+    import torch
+    from . import spdgen_gpu
+    A = spdgen_gpu.gen_spd(n, ratio, 0.0, seed=seed)
+    B = spdgen_gpu.gen_rhs(n, 1, seed=seed + 100)
+    L = torch.empty_like(A)
+    X = torch.empty_like(B)
+    tree = policy_tree(leaf)
+    t0 = time.perf_counter()
+    choice = ctx.policy_choose(A, n, tree, params)
+    torch.cuda.synchronize()
+    choose_ms = (time.perf_counter() - t0) * 1e3
+    trees = {
+        "learned": M.Tree(leaf=leaf, offdiag=[M.F16], scale_mode=1, node_prec=choice),
+        "fixed_f16": M.Tree(leaf=leaf, offdiag=[M.F16]),
+        "fp64": M.Tree(leaf=leaf, offdiag=[M.F64]),
+    }
+    out = {"n": n, "ratio": ratio, "leaf": leaf, "choose_ms": choose_ms,
+           "choice_counts": {nm: choice.count(p) for p, nm in enumerate(("E4M3", "F16", "F32", "F64"))}}
+    for name, t in trees.items():
+        ms = []
+        info = None
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, fi = ctx.factor(A, n, t, L_cm=L, sync=False)
+            _, si = ctx.solve(L, B, n, A_cm=A, tol=1e-13, max_iter=20, X_cm=X)
+            torch.cuda.synchronize()
+            if r:
+                ms.append((time.perf_counter() - a) * 1e3)
+            info = si
+        fl = 0
+        if name == "learned" and info["status"] != 0:
+            fl = 1
+        be = ctx.backward_error(A, ctx.factor(A, n, t, L_cm=L)[0], n)[0]
+        out[name] = {"tts_ms": float(np.median(ms)), "ir_iters": info["ir_iters"],
+                     "status": info["status"], "backward_error": be, "fallback": fl,
+                     "flops_share": {k: v / (n ** 3 / 3) for k, v in M.plan_stats(n, t)["flops"].items()}}
+    out["speedup_learned_vs_fp64"] = out["fp64"]["tts_ms"] / out["learned"]["tts_ms"]
+    out["speedup_learned_vs_fixed"] = out["fixed_f16"]["tts_ms"] / out["learned"]["tts_ms"]
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=20000)
@@ -172,9 +220,18 @@ def main(argv=None) -> int:
     ap.add_argument("--tau", type=float, default=1e-4)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the saved weights")
+    ap.add_argument("--eval-n", type=int, default=32768)
+    ap.add_argument("--eval-ratio", type=float, default=1.1)
     args = ap.parse_args(argv)
+    import json
     import torch
     ctx = M.Context(0)
+    if args.eval_only:
+        res = evaluate(ctx, load_params(args.out), args.eval_n, args.eval_ratio, args.leaf)
+        print(json.dumps(res), flush=True)
+        ctx.close()
+        return 0
     tree = policy_tree(args.leaf)
     ns, ratios, seeds = training_recipe(args.count, args.nmin, args.nmax)
     t0 = time.time()
