@@ -139,10 +139,6 @@ int mpchol_factor(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
  *   max_iter steps, or the correction grows twice in a row.
  *   A == NULL: no refinement (plain substitution solve).
  *   B (n x nrhs, ldb) is not modified; X (n x nrhs, ldx) receives the result.
- * When L is the output of this context's most recent mpchol_factor (same
- * pointer, n and ldl) and that factorization formed leaf inverses (FP64
- * leaves, leaf_trsm 0), the block solves multiply by those inverses (128-row
- * blocks) instead of substituting; L must not have been changed in between.
  * The stream is synchronized once per refinement step and at the end.
  * Errors: -2 n < 0; -3 nrhs < 0; -5 lda; -6 L NULL; -7 ldl; -8 B NULL; -9 ldb;
  * -10 X NULL; -11 ldx; -13 max_iter < 0.

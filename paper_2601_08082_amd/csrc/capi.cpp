@@ -37,12 +37,8 @@ struct mpchol_ctx_s {
   DevStatus* hst = nullptr;   // pinned host copy
   void* ws = nullptr;         // quantized operand copies
   size_t ws_bytes = 0;
-  double* inv = nullptr;      // FP64 leaf inverses (Y, Y^T per slot)
+  double* inv = nullptr;      // FP64 leaf inverses (KL x KL per slot)
   int ninv = 0;
-  // the factor whose leaf inverses `inv` holds (the solve reuses them)
-  const double* inv_L = nullptr;
-  int64_t inv_n = 0, inv_ldl = 0;
-  const Plan* inv_plan = nullptr;
   double* part = nullptr;     // max-abs partials
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
@@ -172,11 +168,9 @@ static void free_plan(Plan& P) {
   if (P.d_maxabs) (void)hipFree(P.d_maxabs);
   if (P.d_casts) (void)hipFree(P.d_casts);
   if (P.d_gemms) (void)hipFree(P.d_gemms);
-  if (P.d_sblocks) (void)hipFree(P.d_sblocks);
   P.d_maxabs = nullptr;
   P.d_casts = nullptr;
   P.d_gemms = nullptr;
-  P.d_sblocks = nullptr;
 }
 
 template <typename T>
@@ -215,7 +209,7 @@ static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, 
   std::unique_ptr<Plan> P(new Plan());
   build_plan(*P, n, ldl, t);
   if (upload(&P->d_maxabs, P->maxabs) || upload(&P->d_casts, P->casts) ||
-      upload(&P->d_gemms, P->gemms) || upload(&P->d_sblocks, P->sblocks)) {
+      upload(&P->d_gemms, P->gemms)) {
     free_plan(*P);
     return MPCHOL_HIP_ERROR;
   }
@@ -236,13 +230,13 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
       case Launch::TRSM:
         if (Lc.first >= 0)
           e = launch_trsm_inv(L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3,
-                              c->inv + (size_t)Lc.first * 2 * kKernelLeaf * kKernelLeaf, s);
+                              c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
         else
           e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
         break;
       case Launch::TRINV:
         e = launch_trinv(L, ldl, Lc.a0, (int)Lc.a1,
-                         c->inv + (size_t)Lc.first * 2 * kKernelLeaf * kKernelLeaf, s);
+                         c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
         break;
       case Launch::MAXABS:
         e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
@@ -608,23 +602,14 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
     if (c->inv) HIPCHK(hipFree(c->inv));
     c->inv = nullptr;
     c->ninv = 0;
-    HIPCHK(hipMalloc((void**)&c->inv,
-                     sizeof(double) * 2 * kKernelLeaf * kKernelLeaf * (size_t)P->ninv));
+    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kKernelLeaf * kKernelLeaf * (size_t)P->ninv));
     c->ninv = P->ninv;
   }
   if (info) HIPCHK(hipEventRecord(c->ev0, s));
   HIPCHK(launch_status_init(c->dst, s));
   if (L != A) HIPCHK(launch_copy_lower(A, lda, L, ldl, n, s));
-  c->inv_L = nullptr;
-  c->inv_plan = nullptr;
   r = run_plan(c, *P, L, ldl, s);
   if (r) return r;
-  if (P->ninv > 0) {
-    c->inv_L = L;
-    c->inv_n = n;
-    c->inv_ldl = ldl;
-    c->inv_plan = P;
-  }
   HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   if (!info) return 0;
   HIPCHK(hipEventRecord(c->ev1, s));
@@ -639,24 +624,6 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
 static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
   const double lbytes = (double)n * (n + 1) / 2 * 8.0;
-  if (c->inv_plan && L == c->inv_L && n == c->inv_n && ldl == c->inv_ldl) {
-    // L is the last factor of this context: solve through its leaf inverses
-    const Plan& P = *c->inv_plan;
-    const int nb = (int)P.sblocks.size();
-    for (int64_t c0 = 0; c0 < nrhs; c0 += 8) {
-      int nc = (int)std::min<int64_t>(8, nrhs - c0);
-      HIPCHK(launch_ticket_reset(c->dst, s));
-      int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-      HIPCHK(launch_trsv_inv(0, L, ldl, nb, P.d_sblocks, c->inv, nc, X + c0 * ldx, ldx, c->dst, 0,
-                             s));
-      prof_end(c, pk, s);
-      pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-      HIPCHK(launch_trsv_inv(1, L, ldl, nb, P.d_sblocks, c->inv, nc, X + c0 * ldx, ldx, c->dst, 2,
-                             s));
-      prof_end(c, pk, s);
-    }
-    return 0;
-  }
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     HIPCHK(launch_ticket_reset(c->dst, s));

@@ -273,8 +273,7 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
 
 // ---------------------------------------------------------------- inverse
 // Y = L^{-1} of the FP64 leaf L = A(i0:i0+m, i0:i0+m), m <= 128, into Y
-// (column-major, ld KL, zero above the diagonal and outside m x m), and its
-// transpose into Y + KL * KL (for the transposed block solves).  L and Y
+// (column-major, ld KL, zero above the diagonal and outside m x m).  L and Y
 // live in LDS as 16 x 16 lower blocks (row-major, padded rows).  Diagonal
 // blocks: column-by-column substitution with true division; off-diagonal
 // blocks by block columns, Y_ij = -Y_ii (sum_{k=j}^{i-1} L_ik Y_kj), with
@@ -370,12 +369,10 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
 #pragma unroll 8
   for (int r = 0; r < KL * KL / 256; r++) {
     const int idx = tid + 256 * r;
-    const int i = idx % KL, j = idx / KL;   // Y(i, j) and Y^T(i, j) = Y(j, i), column-major, ld KL
-    double v = 0.0, w = 0.0;
+    const int i = idx % KL, j = idx / KL;   // Y(i, j), column-major, ld KL
+    double v = 0.0;
     if (i < m && j < m && i >= j) v = y[iblk(i >> 4, j >> 4) + (i & 15) * IBP + (j & 15)];
-    if (i < m && j < m && j >= i) w = y[iblk(j >> 4, i >> 4) + (j & 15) * IBP + (i & 15)];
     Y[i + j * KL] = v;
-    Y[KL * KL + i + j * KL] = w;
   }
 }
 

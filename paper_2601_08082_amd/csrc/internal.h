@@ -85,24 +85,12 @@ hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,
                             int64_t c0, int k, hipStream_t s);
 
-// A diagonal block of the block triangular solves: a kernel leaf of the
-// factorization and its inverse slot (Y, Y^T: 2 x KL x KL doubles).
-struct SolveBlock {
-  int64_t i0;
-  int32_t m, slot;
-};
-
 // Solve / refinement kernels.
 hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs,
                        double* X, int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s);
 // R = B - A X (A symmetric, lower stored, read once); work holds
 // residual_work_bytes(n, nrhs) bytes of tile partials.
 size_t residual_work_bytes(int64_t n, int nrhs);
-// Block triangular solve through the leaf inverses (blocks of <= KL rows,
-// nrhs <= 8): X <- L^{-1} X (trans 0) or L^{-T} X (trans 1).
-hipError_t launch_trsv_inv(int trans, const double* Lm, int64_t ldl, int nblk,
-                           const SolveBlock* blocks, const double* inv, int nrhs, double* X,
-                           int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
                            double* work, hipStream_t s);

@@ -186,125 +186,6 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
   }
 }
 
-// Block solves through the leaf inverses: the diagonal blocks are the
-// factorization's kernel leaves (<= 128 rows) and x_J = Y_J (b_J - sum_K
-// L(J, K) x_K) (forward) or x_J = Y_J^T (b_J - sum_K L(K, J)^T x_K)
-// (transposed), so the critical path per block is a matrix-vector product
-// instead of a column chain, and there are half as many blocks as in the
-// 64-row kernel.  Ticketing, waits and publication as in k_trsv.  Thread
-// (r, h) = (tid % 128, tid / 128) owns row r and the columns of parity h.
-constexpr int KB2 = kKernelLeaf;   // 128
-
-template <int NR>
-__global__ __launch_bounds__(256) void k_trsv_inv(int trans, const double* __restrict__ Lm,
-                                                  int64_t ldl, int nblk,
-                                                  const SolveBlock* __restrict__ blocks,
-                                                  const double* __restrict__ inv, int nrhs,
-                                                  double* X, int64_t ldx, DevStatus* st,
-                                                  int slot) {
-  __shared__ double blk[KB2][KB2 + 1];   // transposed case: blk[c][i] = L(k0 + i, j0 + c)
-  __shared__ double xs[KB2][NR];
-  __shared__ double acc[2][KB2][NR];
-  __shared__ unsigned int my_ticket;
-  const int tid = threadIdx.x, r = tid & (KB2 - 1), h = tid >> 7;
-  if (tid == 0) my_ticket = atomicAdd(&st->ticket[slot], 1u);
-  __syncthreads();
-  const int t = (int)my_ticket;
-  unsigned int* done = &st->ticket[slot + 1];
-  const int J = trans ? nblk - 1 - t : t;
-  const SolveBlock SB = blocks[J];
-  const int64_t j0 = SB.i0;
-  const int nj = SB.m;
-  // this block's inverse row r (Y, or Y^T when transposed), columns of parity h
-  const double* Y = inv + (size_t)SB.slot * 2 * KB2 * KB2 + (trans ? KB2 * KB2 : 0);
-  double yv[KB2 / 2];
-#pragma unroll
-  for (int u = 0; u < KB2 / 2; u++) yv[u] = Y[r + (2 * u + h) * KB2];   // zero outside nj x nj
-  double part[NR];
-#pragma unroll
-  for (int c = 0; c < NR; c++) part[c] = 0.0;
-  for (int s = 0; s < t; s++) {
-    const int K = trans ? nblk - 1 - s : s;
-    const SolveBlock KBk = blocks[K];
-    const int64_t k0 = KBk.i0;
-    const int nk = KBk.m;
-    double lv[KB2 / 2];
-    if (!trans) {
-      // L(j0 + r, k0 + q), q = 2u + h: lanes along rows
-#pragma unroll
-      for (int u = 0; u < KB2 / 2; u++) {
-        const int q = 2 * u + h;
-        const double v = Lm[(j0 + min(r, nj - 1)) + (k0 + min(q, nk - 1)) * ldl];
-        lv[u] = (r < nj && q < nk) ? v : 0.0;
-      }
-    } else {
-      // L(k0 + i, j0 + c) with i = r, c = 2u + h: lanes along rows of the K block
-#pragma unroll
-      for (int u = 0; u < KB2 / 2; u++) {
-        const int c = 2 * u + h;
-        const double v = Lm[(k0 + min(r, nk - 1)) + (j0 + min(c, nj - 1)) * ldl];
-        lv[u] = (r < nk && c < nj) ? v : 0.0;
-      }
-    }
-    if (!wait_done(done, (unsigned)s, st)) return;
-    for (int idx = tid; idx < KB2 * NR; idx += 256) {
-      const int i = idx % KB2, c = idx / KB2;
-      xs[i][c] = (i < nk && c < nrhs) ? coherent_load(&X[(k0 + i) + (int64_t)c * ldx]) : 0.0;
-    }
-    if (trans) {
-#pragma unroll
-      for (int u = 0; u < KB2 / 2; u++) blk[2 * u + h][r] = lv[u];
-    }
-    __syncthreads();
-    if (!trans) {
-#pragma unroll
-      for (int u = 0; u < KB2 / 2; u++)
-#pragma unroll
-        for (int c = 0; c < NR; c++) part[c] += lv[u] * xs[2 * u + h][c];
-    } else {
-      // part[r] += sum over rows i = 2u + h of L(k0 + i, j0 + r) x(k0 + i)
-#pragma unroll 8
-      for (int u = 0; u < KB2 / 2; u++) {
-        const double l = blk[r][2 * u + h];
-#pragma unroll
-        for (int c = 0; c < NR; c++) part[c] += l * xs[2 * u + h][c];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int c = 0; c < NR; c++) acc[h][r][c] = part[c];
-  __syncthreads();
-  if (tid < KB2) {
-#pragma unroll
-    for (int c = 0; c < NR; c++) {
-      const double b = (r < nj && c < nrhs) ? X[(j0 + r) + (int64_t)c * ldx] : 0.0;
-      xs[r][c] = r < nj ? b - (acc[0][r][c] + acc[1][r][c]) : 0.0;
-    }
-  }
-  __syncthreads();
-  double xv[NR];
-#pragma unroll
-  for (int c = 0; c < NR; c++) xv[c] = 0.0;
-#pragma unroll
-  for (int u = 0; u < KB2 / 2; u++)
-#pragma unroll
-    for (int c = 0; c < NR; c++) xv[c] += yv[u] * xs[2 * u + h][c];
-#pragma unroll
-  for (int c = 0; c < NR; c++) acc[h][r][c] = xv[c];
-  __syncthreads();
-  if (tid < KB2 && r < nj) {
-#pragma unroll
-    for (int c = 0; c < NR; c++)
-      if (c < nrhs) X[(j0 + r) + (int64_t)c * ldx] = acc[0][r][c] + acc[1][r][c];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // R = B - A X, A symmetric with its lower triangle stored, every stored
 // element read once (the diagonal tiles' lower halves twice).  Pass 1: workgroup (c, I) takes the lower tiles (I, J)
 // of row block I with J in chunk c ([RCH c, RCH c + RCH), J <= I); each
@@ -517,27 +398,6 @@ static void resid_launch(const double* A, int64_t lda, int64_t n, int nrhs, cons
                      n, nrhs, X, ldx, rowp, colp);
   hipLaunchKernelGGL(k_resid_reduce<NR>, dim3((unsigned)nblk), dim3(256), 0, s, n, nrhs, rowp, colp,
                      B, ldb, R, ldr);
-}
-
-hipError_t launch_trsv_inv(int trans, const double* Lm, int64_t ldl, int nblk,
-                           const SolveBlock* blocks, const double* inv, int nrhs, double* X,
-                           int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s) {
-  if (nblk <= 0 || nrhs <= 0) return hipSuccess;
-  if (nrhs > 8 || (ticket_slot != 0 && ticket_slot != 2)) return hipErrorInvalidValue;
-  dim3 g(nblk), b(256);
-  if (nrhs == 1)
-    hipLaunchKernelGGL(k_trsv_inv<1>, g, b, 0, s, trans, Lm, ldl, nblk, blocks, inv, nrhs, X, ldx, st,
-                       ticket_slot);
-  else if (nrhs <= 2)
-    hipLaunchKernelGGL(k_trsv_inv<2>, g, b, 0, s, trans, Lm, ldl, nblk, blocks, inv, nrhs, X, ldx, st,
-                       ticket_slot);
-  else if (nrhs <= 4)
-    hipLaunchKernelGGL(k_trsv_inv<4>, g, b, 0, s, trans, Lm, ldl, nblk, blocks, inv, nrhs, X, ldx, st,
-                       ticket_slot);
-  else
-    hipLaunchKernelGGL(k_trsv_inv<8>, g, b, 0, s, trans, Lm, ldl, nblk, blocks, inv, nrhs, X, ldx, st,
-                       ticket_slot);
-  return hipGetLastError();
 }
 
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,

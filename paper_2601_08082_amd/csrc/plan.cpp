@@ -278,7 +278,6 @@ struct Builder {
         I.a1 = m;
         I.first = P.ninv++;
         inv_slot[i0] = {I.first, m};
-        P.sblocks.push_back(SolveBlock{i0, (int32_t)m, I.first});
         P.launches.push_back(I);
       }
       return;

@@ -37,14 +37,12 @@ struct Plan {
   std::vector<GemmProb> gemms;
   size_t ws_bytes = 0;     // quantized-operand workspace needed
   int64_t parts = 0;       // maxabs partial slots needed
-  int ninv = 0;            // leaf-inverse slots (Y and Y^T: 2 x KL x KL doubles each)
-  std::vector<SolveBlock> sblocks;   // kernel leaves in diagonal order, with their slots
+  int ninv = 0;            // leaf-inverse slots (KL x KL doubles each)
   PlanStats stats;
   // device copies of the descriptor arrays
   MaxabsJob* d_maxabs = nullptr;
   CastJob* d_casts = nullptr;
   GemmProb* d_gemms = nullptr;
-  SolveBlock* d_sblocks = nullptr;
 };
 
 // Validates the descriptor; returns 0 or a negative/positive mpchol code.

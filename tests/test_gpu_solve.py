@@ -137,31 +137,3 @@ def test_full_size_16384_mixed_tree(M, ctx):
     lam = spdgen.gershgorin_lower_bound(n, ratio, 0.0, A)
     assert lam > 0
     assert np.linalg.norm(r) / lam <= 1e-12 * np.linalg.norm(x)
-
-
-@pytest.mark.parametrize("n,nrhs,leaf", [(300, 1, 64), (1000, 3, 128), (777, 10, 200)])
-def test_inverse_block_solve_vs_substitution(M, ctx, n, nrhs, leaf):
-    """A solve right after its factorization runs through the leaf inverses;
-    the same L in another buffer takes the substitution kernel.  Both agree
-    to FP64 rounding."""
-    import torch
-    print(f"[gpu] inverse block solve n={n} nrhs={nrhs}", flush=True)
-    A = spdgen.gen_spd(n, 1.3, 0.0, seed=n + 9)
-    B = M.to_device_cm(spdgen.gen_rhs(n, nrhs, seed=17))
-    Ad = M.to_device_cm(A)
-    L, info = ctx.factor(Ad, n, M.Tree(leaf=leaf, offdiag=[M.F16]))
-    assert info["status"] == 0
-    Linv_path = L                           # the context's last factor: inverse blocks
-    Lcopy = L.clone()                       # another buffer: substitution blocks
-    X1, s1 = ctx.solve(Lcopy, B, n)
-    X2, s2 = ctx.solve(Linv_path, B, n)
-    assert s1["status"] == 0 and s2["status"] == 0
-    x1, x2 = M.from_device_cm(X1)[:n], M.from_device_cm(X2)[:n]
-    assert np.max(np.linalg.norm(x1 - x2, axis=0) / np.linalg.norm(x1, axis=0)) <= 1e-14
-    # refined solves through both paths reach the FP64 solution
-    xs = np.linalg.solve(A[:n, :n], M.from_device_cm(B)[:n])
-    for Lx in (Lcopy, Linv_path):
-        X, si = ctx.solve(Lx, B, n, A_cm=Ad, tol=1e-13, max_iter=20)
-        assert si["status"] == 0
-        x = M.from_device_cm(X)[:n]
-        assert np.max(np.linalg.norm(x - xs, axis=0) / np.linalg.norm(xs, axis=0)) <= 1e-12
