@@ -194,7 +194,9 @@ def bench_batched(args) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "large", "batched"], default="single",
+                    help="single: n=16384 ratio 1.5 [F16,F16,F32x4] 1 rhs; large: n=65536 ratio "
+                         "1.2 [F16,F32,F64] 16 rhs; batched: 4096 uneven systems")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -223,13 +225,22 @@ def main() -> int:
     n, ratio = args.n, args.ratio
     leaf = 256
     mixed_levels = [M.F16, M.F16, M.F32, M.F32, M.F32, M.F32]
+    nrhs = 1
+    if args.workload == "large":
+        if n == 16384:
+            n = 65536
+        if ratio == 1.5:
+            ratio = 1.2
+        mixed_levels = [M.F16, M.F32, M.F64]
+        nrhs = 16
+        args.no_cpu_baseline = True
     tree = M.Tree(leaf=leaf, offdiag=mixed_levels, leaf_prec=M.F64)
     tree64 = M.Tree(leaf=leaf, offdiag=[M.F64], leaf_prec=M.F64)
     flops = n ** 3 / 3.0
 
     ctx = M.Context(0)
     A = spdgen_gpu.gen_spd(n, ratio, 0.0, seed=8, lda=n)
-    B = spdgen_gpu.gen_rhs(n, 1, seed=108, ldb=n)
+    B = spdgen_gpu.gen_rhs(n, nrhs, seed=108, ldb=n)
     L = torch.empty_like(A)
     X = torch.empty_like(B)
     torch.cuda.synchronize()
@@ -274,16 +285,20 @@ def main() -> int:
         fms.append((time.perf_counter() - a) * 1e3)
     factor_ms = float(np.median(fms))
 
-    # solution check: Gershgorin certificate with the FP64 residual (GPU data, CPU arithmetic)
+    # solution check (outside the timed region): Gershgorin certificate
+    # ||x - x*|| <= ||b - A x|| / lambda_min with the FP64 residual, and the
+    # factor's backward error, both computed on the device
     s = step(tree)
     torch.cuda.synchronize()
-    Ah = A.cpu().numpy()
-    x = X.cpu().numpy()[0]
-    b = B.cpu().numpy()[0]
-    r = b - Ah @ x
-    lam = spdgen.gershgorin_lower_bound(n, ratio, 0.0, Ah)
-    cert = float(np.linalg.norm(r) / lam / np.linalg.norm(x))
-    del Ah
+    with torch.no_grad():
+        Acm = A[:n, :n]                      # A symmetric: the stored block is A itself
+        R = B[:nrhs, :n] - X[:nrhs, :n] @ Acm
+        dg = torch.diagonal(Acm)
+        lam = float(torch.min(dg - (Acm.abs().sum(dim=1) - dg.abs())).item())
+        cert = float(torch.max(torch.linalg.vector_norm(R, dim=1) / lam /
+                               torch.linalg.vector_norm(X[:nrhs, :n], dim=1)).item())
+        del R
+    be_factor = ctx.backward_error(A, L, n)[0]
 
     fp64 = None
     if not args.no_fp64:
@@ -324,14 +339,17 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f16/f32 MFMA (f32 acc) + f64 leaves, f64 in/out",
         "data": "synthetic",
-        "config": {"workload": f"SPD n={n} dominance ratio {ratio}, tree [F16,F16,F32,F32,F32,F32] "
-                               f"leaf {leaf} FP64, 1 rhs, FP64-residual refinement to 1e-13 correction",
-                   "n": n, "leaf": leaf, "nrhs": 1, "parallelism": "single GPU"},
+        "config": {"workload": f"SPD n={n} dominance ratio {ratio}, tree "
+                               f"[{','.join(M.PREC_LABELS[p] for p in mixed_levels)}] "
+                               f"leaf {leaf} FP64, {nrhs} rhs, FP64-residual refinement to 1e-13 "
+                               f"correction",
+                   "n": n, "leaf": leaf, "nrhs": nrhs, "parallelism": "single GPU"},
         "time_to_solution_ms": ms_step,
         "factor_ms": factor_ms,
         "factor_tflops": flops / (factor_ms * 1e-3) / 1e12,
         "ir_iters": int(np.median(iters)),
         "solution_error_certificate": cert,
+        "backward_error": be_factor,
         "fp64_path": fp64,
         "plan": {"launches": stats["launches"], "ws_gb": stats["ws_bytes"] / 1e9,
                  "flop_share": {k: v / flops for k, v in stats["flops"].items()}},

@@ -26,6 +26,7 @@ OK, NOT_SPD, NONFINITE, NOT_CONVERGED, HIP_ERROR, NOT_SUPPORTED = 0, 1, 2, 3, 4,
 PROF_KINDS = ["gemm_e4m3", "gemm_f16", "gemm_f32", "gemm_f64", "cast", "maxabs", "potrf", "trsm",
               "trsv", "residual", "trinv"]
 ABI_VERSION = 2
+PREC_LABELS = {0: "E4M3", 1: "F16", 2: "F32", 3: "F64"}
 MAX_LEVELS = 24
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
