@@ -6,10 +6,11 @@ module only generates the synthetic training matrices, shuffles minibatches
 on the host and strings the calls together.
 
 Training set (one row per internal Tree-POTRF node): `count` matrices of the
-seeded generator with n log-uniform in [nmin, nmax] (multiples of 256) and
-dominance ratio log-uniform in [rmin, rmax]; features from A, labels from an
-FP64 factor of A (the cheapest precision whose quantization error of the
-node's L21 block fits the node's share of the error budget tau).
+seeded generator with n log-uniform in [nmin, nmax] (multiples of 256),
+dominance ratio log-uniform in [rmin, rmax] and leaf size 64, 128 or 256;
+features from A, labels from an FP64 factor of A (the cheapest precision
+whose quantization error of the node's L21 block fits the node's share of the
+error budget tau).
 
 Inference: the perceptron picks each node's precision; the factor runs with
 scale_mode 1 (power-of-two scaling both ways, needed by E4M3).  If the
@@ -63,14 +64,28 @@ def training_recipe(count: int, nmin: int = 1024, nmax: int = 8192, rmin: float 
     return [int(n) for n in ns], [float(r) for r in ratios], [seed * 100_003 + i for i in range(count)]
 
 
-def build_dataset(ctx, ns, ratios, seeds, tree, tau: float = 1e-4, log_every: int = 0):
-    """Features (rows, 5) float32 and labels (rows,) int32, as device tensors."""
+def leaf_mix(count: int, seed: int = 7, leaves=(64, 128, 256)):
+    """Leaf size per training matrix: smaller leaves put deep nodes (depth up
+    to 6-7 at n = 8192) into the training set, as deep as the leaf-256 tree of
+    an n = 32768 system goes."""
+    rng = np.random.default_rng(seed)
+    return [int(b) for b in rng.choice(leaves, count)]
+
+
+def build_dataset(ctx, ns, ratios, seeds, tree, tau: float = 1e-4, log_every: int = 0,
+                  leaves=None):
+    """Features (rows, 5) float32 and labels (rows,) int32, as device tensors.
+    leaves: optional per-matrix leaf sizes (else the tree's)."""
+    import dataclasses
+
     import torch
     from . import spdgen_gpu
-    t64 = M.Tree(leaf=tree.leaf, offdiag=[M.F64], leaf_prec=M.F64, split_align=tree.split_align)
     feats, labs = [], []
     t0 = time.time()
+    base = tree
     for i, (n, r, sd) in enumerate(zip(ns, ratios, seeds)):
+        tree = dataclasses.replace(base, leaf=leaves[i]) if leaves else base
+        t64 = M.Tree(leaf=tree.leaf, offdiag=[M.F64], leaf_prec=M.F64, split_align=tree.split_align)
         A = spdgen_gpu.gen_spd(n, r, 0.0, seed=sd)
         L, info = ctx.factor(A, n, t64)
         if info["status"] != 0:
@@ -204,6 +219,12 @@ def evaluate(ctx, params, n: int = 32768, ratio: float = 1.1, leaf: int = 256, r
         out[name] = {"tts_ms": float(np.median(ms)), "ir_iters": info["ir_iters"],
                      "status": info["status"], "backward_error": be, "fallback": fl,
                      "flops_share": {k: v / (n ** 3 / 3) for k, v in M.plan_stats(n, t)["flops"].items()}}
+    # the labels of this matrix (from its FP64 factor) against the network's choice
+    L64, _ = ctx.factor(A, n, trees["fp64"], L_cm=L)
+    lab, _ = ctx.policy_labels(A, L64, n, tree, tau=1e-4, scale_mode=1)
+    lab = lab.cpu().numpy().tolist()
+    out["label_counts"] = {nm: lab.count(p) for p, nm in enumerate(("E4M3", "F16", "F32", "F64"))}
+    out["choice_matches_labels"] = float(np.mean(np.array(lab) == np.array(choice)))
     out["speedup_learned_vs_fp64"] = out["fp64"]["tts_ms"] / out["learned"]["tts_ms"]
     out["speedup_learned_vs_fixed"] = out["fixed_f16"]["tts_ms"] / out["learned"]["tts_ms"]
     return out
@@ -221,6 +242,8 @@ def main(argv=None) -> int:
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--eval-only", action="store_true", help="evaluate the saved weights")
+    ap.add_argument("--mixed-leaves", type=int, default=1,
+                    help="1: leaf 64/128/256 per training matrix; 0: the --leaf of every matrix")
     ap.add_argument("--eval-n", type=int, default=32768)
     ap.add_argument("--eval-ratio", type=float, default=1.1)
     args = ap.parse_args(argv)
@@ -235,13 +258,15 @@ def main(argv=None) -> int:
     tree = policy_tree(args.leaf)
     ns, ratios, seeds = training_recipe(args.count, args.nmin, args.nmax)
     t0 = time.time()
-    X, y = build_dataset(ctx, ns, ratios, seeds, tree, args.tau, log_every=max(1, args.count // 20))
+    X, y = build_dataset(ctx, ns, ratios, seeds, tree, args.tau, log_every=max(1, args.count // 20),
+                         leaves=leaf_mix(args.count) if args.mixed_leaves else None)
     counts = np.bincount(y.cpu().numpy(), minlength=4)
     print(f"[policy] {X.shape[0]} nodes, label counts E4M3/F16/F32/F64 = {counts.tolist()}, "
           f"{time.time() - t0:.1f} s", flush=True)
     nv = max(1, args.count // 10)
     vns, vr, vs = training_recipe(nv, args.nmin, args.nmax, seed=6)
-    Xv, yv = build_dataset(ctx, vns, vr, vs, tree, args.tau)
+    Xv, yv = build_dataset(ctx, vns, vr, vs, tree, args.tau,
+                           leaves=leaf_mix(nv, seed=8) if args.mixed_leaves else None)
     params, hist = train(ctx, X, y, args.epochs, args.batch, args.lr,
                          log_every=max(1, args.epochs // 10))
     print(f"[policy] train accuracy {accuracy(ctx, X, y, params):.4f}, validation accuracy "
