@@ -76,6 +76,8 @@ struct mpchol_ctx_s {
   std::vector<std::pair<void*, size_t>> pbuf;
 };
 
+static_assert(MPCHOL_PROF_KINDS == 11, "per-class slots of the persistent kernel's timing");
+
 static void free_batch(mpchol_ctx c) {
   auto& B = c->bt;
   if (B.exec) (void)hipGraphExecDestroy(B.exec);

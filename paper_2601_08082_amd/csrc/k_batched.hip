@@ -20,6 +20,7 @@ namespace mpc {
 namespace {
 
 constexpr int kPool = trsm_leaf_lds_bytes<double>();  // largest body
+constexpr int kProfClasses = 11;                       // per-class timing slots (public numbering)
 static_assert(kPool >= potrf_leaf_lds_bytes<double>(), "pool");
 static_assert(kPool >= gemm_q_lds_bytes<_Float16, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<double, 128>(), "pool");
@@ -492,7 +493,7 @@ __global__ __launch_bounds__(256) void k_batched(BatchProgram prog) {
 
 __global__ void k_queue_reset(unsigned int* q, unsigned long long* prof) {
   if (threadIdx.x == 0) *q = 0u;
-  if (prof && threadIdx.x < 20) prof[threadIdx.x] = 0ull;
+  if (prof && threadIdx.x < 2 * kProfClasses) prof[threadIdx.x] = 0ull;
 }
 
 }  // namespace
