@@ -98,6 +98,7 @@ static int launch_kind(const Launch& L) {
     case Launch::MAXABS: return MPCHOL_PROF_MAXABS;
     case Launch::POTRF: return MPCHOL_PROF_POTRF;
     case Launch::TRINV: return MPCHOL_PROF_TRINV;
+    case Launch::CASTFIX: return MPCHOL_PROF_MAXABS;
     default: return MPCHOL_PROF_TRSM;
   }
 }
@@ -158,6 +159,8 @@ static double launch_work(const Plan& P, const Launch& L) {
       const MaxabsJob& j = P.maxabs[L.first + i];
       w += (double)j.rows * j.cols * 8.0;
     }
+  } else if (L.kind == Launch::CASTFIX) {
+    for (int i = 0; i < L.count; i++) w += (double)P.casts[L.first + i].nparts * 8.0;
   } else if (L.kind == Launch::POTRF || L.kind == Launch::TRINV) {
     w = (double)L.a1 * L.a1 * L.a1 / 3.0;
   } else {
@@ -244,8 +247,16 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
         e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
         break;
       case Launch::CAST:
-        e = launch_cast(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec, sm,
-                        c->ws, c->dst, s);
+        if (Lc.a0 == 1)
+          e = launch_cast_max(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec,
+                              c->ws, s);
+        else
+          e = launch_cast(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec, sm,
+                          c->ws, c->dst, s);
+        break;
+      case Launch::CASTFIX:
+        e = launch_cast_fixup(L, ldl, P.d_casts + Lc.first, Lc.count, c->part, Lc.prec, c->ws,
+                              c->dst, s);
         break;
       case Launch::GEMM:
         e = launch_gemm(Lc.prec, Lc.tile, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count,
@@ -835,7 +846,8 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         build_plan(P, n_host[i], ldl_host[i], &t, true, tile);
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
-          if (L.kind == Launch::TRINV || (L.kind == Launch::TRSM && L.first >= 0)) {
+          if (L.kind == Launch::TRINV || L.kind == Launch::CASTFIX ||
+              (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0)) {
             free_batch(c);
             return MPCHOL_HIP_ERROR;   // workgroup-level plans never use leaf inverses
           }

@@ -53,31 +53,37 @@ __device__ inline double reduce_parts(const double* __restrict__ part, int p0, i
 template <typename Q>
 constexpr int cast_lds_bytes() { return 256 * 8 + 64 * (64 + 8) * (int)sizeof(Q); }
 
-// Tile t (64 x 64) of the job's transposing quantize.
+// Tile t (64 x 64) of a job's transposing quantize with block scale 1 / inv_s:
+// all loads of a thread in flight, then 16-byte (FP16) / 8-byte (E4M3) row
+// stores of the K-contiguous copy.  With want_max, returns the tile's max |x|
+// (NaN/Inf -> +Inf) to every thread (red: 256 doubles of LDS).
 template <typename Q>
-__device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
-                                 int t, const double* __restrict__ part, int prec,
-                                 int scale_mode, Q* __restrict__ ws, DevStatus* st, char* lds) {
-  double* red = reinterpret_cast<double*>(lds);
+__device__ inline double cast_core(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
+                                   int t, double inv_s, int prec, Q* __restrict__ ws, double* red,
+                                   char* tile_lds, bool want_max) {
   typedef Q Row[64 + 8];
-  Row* tile = reinterpret_cast<Row*>(red + 256);
-  __syncthreads();
-  int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
-  double maxabs = reduce_parts(part, jb.part0, jb.nparts, red);
-  bool bad = !(maxabs <= 1.7976931348623157e308);
-  double s = bad ? 1.0 : block_scale(maxabs, prec, scale_mode);
-  double inv_s = 1.0 / s;  // exact: s is a power of two
-  if (bad && threadIdx.x == 0) atomicOr(&st->nonfinite, 1u);
-  int r0 = tr * 64, c0 = tc * 64;
-  // load: thread -> row (t % 64), columns (t / 64) + 4 i
-  int rr = threadIdx.x & 63;
+  Row* tile = reinterpret_cast<Row*>(tile_lds);
+  const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
+  const int r0 = tr * 64, c0 = tc * 64;
+  const int rr = threadIdx.x & 63;
+  double v[16];
+#pragma unroll
   for (int i = 0; i < 16; i++) {
-    int cc = (threadIdx.x >> 6) + 4 * i;
-    int r = r0 + rr, c = c0 + cc;
+    const int cc = (threadIdx.x >> 6) + 4 * i;
+    const int r = min(r0 + rr, jb.rows - 1), c = min(c0 + cc, jb.cols - 1);
+    v[i] = Lm[jb.src + r + (int64_t)c * ldl];
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    const int cc = (threadIdx.x >> 6) + 4 * i;
+    const bool in = r0 + rr < jb.rows && c0 + cc < jb.cols;
     uint32_t bits = 0u;
-    if (r < jb.rows && c < jb.cols) {
-      double v = Lm[jb.src + r + (int64_t)c * ldl] * inv_s;
-      bits = encode_bits(v, prec);
+    if (in) {
+      double a = fabs(v[i]);
+      if (!(a <= 1.7976931348623157e308)) a = __longlong_as_double(0x7FF0000000000000ll);
+      m = fmax(m, a);
+      bits = encode_bits(v[i] * inv_s, prec);
     }
     Q q;
     if constexpr (sizeof(Q) == 2) {
@@ -89,12 +95,81 @@ __device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, con
     }
     tile[rr][cc] = q;
   }
+  if (want_max) {
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+      __syncthreads();
+    }
+    m = red[0];
+  } else {
+    __syncthreads();
+  }
+  // rows of the copy: 8 consecutive elements per store (chunks never straddle ldq,
+  // which is a multiple of 16)
+  for (int idx = threadIdx.x; idx < 64 * 8; idx += 256) {
+    const int r = idx >> 3, ch = (idx & 7) * 8;
+    const int gr = r0 + r, gc = c0 + ch;
+    if (gr < jb.rows && gc < jb.ldq) {
+      Q* dst = ws + jb.dst + (int64_t)gr * jb.ldq + gc;
+      if constexpr (sizeof(Q) == 2) {
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&tile[r][ch]);
+      } else {
+        *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(&tile[r][ch]);
+      }
+    }
+  }
+  return m;
+}
+
+// Tile t (64 x 64) of the job's transposing quantize, with the block scale
+// from the job's max-abs partials.
+template <typename Q>
+__device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
+                                 int t, const double* __restrict__ part, int prec,
+                                 int scale_mode, Q* __restrict__ ws, DevStatus* st, char* lds) {
+  double* red = reinterpret_cast<double*>(lds);
   __syncthreads();
-  // store rows of the copy: 64 columns of row r are contiguous
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    int r = idx >> 6, c = idx & 63;
-    int gr = r0 + r, gc = c0 + c;
-    if (gr < jb.rows && gc < jb.ldq) ws[jb.dst + (int64_t)gr * jb.ldq + gc] = tile[r][c];
+  const double maxabs = reduce_parts(part, jb.part0, jb.nparts, red);
+  const bool bad = !(maxabs <= 1.7976931348623157e308);
+  const double s = bad ? 1.0 : block_scale(maxabs, prec, scale_mode);
+  if (bad && threadIdx.x == 0) atomicOr(&st->nonfinite, 1u);
+  cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);  // 1/s exact
+}
+
+// Scale-1 cast that also records the tile's max |x| in part[jb.part0 + t]: the
+// first half of the single-pass quantization (scale_mode 0: a block whose
+// max |x| fits the format has scale 1).
+template <typename Q>
+__device__ inline void cast_max_tile(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
+                                     int t, double* __restrict__ part, int prec,
+                                     Q* __restrict__ ws, char* lds) {
+  double* red = reinterpret_cast<double*>(lds);
+  __syncthreads();
+  const double m = cast_core<Q>(Lm, ldl, jb, t, 1.0, prec, ws, red, lds + 256 * 8, true);
+  if (threadIdx.x == 0) part[jb.part0 + t] = m;
+}
+
+// Second half, one workgroup per job: the block max |x| from the tile partials
+// into part[jb.final_part]; a block whose scale is not 1 is cast again with it.
+template <typename Q>
+__device__ inline void cast_fixup_job(const double* __restrict__ Lm, int64_t ldl,
+                                      const CastJob& jb, double* __restrict__ part, int prec,
+                                      Q* __restrict__ ws, DevStatus* st, char* lds) {
+  double* red = reinterpret_cast<double*>(lds);
+  __syncthreads();
+  const double maxabs = reduce_parts(part, jb.part0, jb.nparts, red);
+  const bool bad = !(maxabs <= 1.7976931348623157e308);
+  if (threadIdx.x == 0) part[jb.final_part] = maxabs;
+  if (bad && threadIdx.x == 0) atomicOr(&st->nonfinite, 1u);
+  const double s = bad ? 1.0 : block_scale(maxabs, prec, 0);
+  if (s != 1.0) {
+    const int ntiles = jb.tiles_r * jb.tiles_c;
+    for (int t = 0; t < ntiles; t++) {
+      __syncthreads();
+      cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);
+    }
   }
 }
 

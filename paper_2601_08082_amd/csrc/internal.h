@@ -44,6 +44,7 @@ struct CastJob {
   int32_t tiles_r;   // 64-row tiles
   int32_t tiles_c;   // 64-col tiles over ldq
   int32_t wg_start;
+  int32_t final_part;  // single-pass cast: slot of the block's max |x| (else -1)
 };
 
 // One GEMM problem of a grouped launch:  C(m x n) -= sx*sy * X(m x k) Y(n x k)^T
@@ -72,6 +73,13 @@ hipError_t launch_maxabs(const double* Lm, int64_t ldl, const MaxabsJob* jobs, i
 hipError_t launch_cast(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                        int total_wg, const double* part, int prec, int scale_mode, void* ws,
                        DevStatus* st, hipStream_t s);
+// Single-pass quantization (FP16, scale_mode 0): scale-1 cast with per-tile
+// max-abs partials, then one workgroup per job finalizes the block max-abs
+// and re-casts the rare block whose scale is not 1.
+hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
+                           int total_wg, double* part, int prec, void* ws, hipStream_t s);
+hipError_t launch_cast_fixup(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
+                             double* part, int prec, void* ws, DevStatus* st, hipStream_t s);
 hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* ws,
                        const GemmProb* probs, int nprobs, int total_tiles, const double* part,
                        int scale_mode, DevStatus* st, hipStream_t s);

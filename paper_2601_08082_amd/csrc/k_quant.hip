@@ -1,6 +1,9 @@
 // Quantization kernels (Section 3.4): block max-abs, power-of-two scale and the
-// fused FP64 -> FP16 / E4M3 transposing cast into a K-contiguous workspace copy;
-// plus the small housekeeping kernels of a factorization.
+// fused FP64 -> FP16 / E4M3 transposing cast into a K-contiguous workspace copy
+// (two passes: max-abs, then cast; or, for FP16 with scale_mode 0, one pass
+// at scale 1 that records the max-abs, and a per-block fix-up that re-casts
+// the rare block whose scale is not 1 - same values either way); plus the
+// small housekeeping kernels of a factorization.
 #include "dev_quant.h"
 
 namespace mpc {
@@ -59,6 +62,54 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ Lm, int
     if (jobs[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
   }
   cast_tile<Q>(Lm, ldl, jobs[lo], wg - jobs[lo].wg_start, part, prec, scale_mode, ws, st, pool);
+}
+
+template <typename Q>
+__global__ __launch_bounds__(256) void k_cast_max(const double* __restrict__ Lm, int64_t ldl,
+                                                  const CastJob* __restrict__ jobs, int njobs,
+                                                  double* __restrict__ part, int prec,
+                                                  Q* __restrict__ ws) {
+  __shared__ __attribute__((aligned(16))) char pool[cast_lds_bytes<Q>()];
+  int wg = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
+  }
+  cast_max_tile<Q>(Lm, ldl, jobs[lo], wg - jobs[lo].wg_start, part, prec, ws, pool);
+}
+
+template <typename Q>
+__global__ __launch_bounds__(256) void k_cast_fixup(const double* __restrict__ Lm, int64_t ldl,
+                                                    const CastJob* __restrict__ jobs,
+                                                    double* __restrict__ part, int prec,
+                                                    Q* __restrict__ ws, DevStatus* st) {
+  __shared__ __attribute__((aligned(16))) char pool[cast_lds_bytes<Q>()];
+  cast_fixup_job<Q>(Lm, ldl, jobs[blockIdx.x], part, prec, ws, st, pool);
+}
+
+hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
+                           int total_wg, double* part, int prec, void* ws, hipStream_t s) {
+  if (njobs <= 0 || total_wg <= 0) return hipSuccess;
+  if (prec == F16)
+    hipLaunchKernelGGL(k_cast_max<_Float16>, dim3(total_wg), dim3(256), 0, s, Lm, ldl, jobs, njobs,
+                       part, prec, (_Float16*)ws);
+  else
+    hipLaunchKernelGGL(k_cast_max<unsigned char>, dim3(total_wg), dim3(256), 0, s, Lm, ldl, jobs,
+                       njobs, part, prec, (unsigned char*)ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_fixup(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
+                             double* part, int prec, void* ws, DevStatus* st, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  if (prec == F16)
+    hipLaunchKernelGGL(k_cast_fixup<_Float16>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs, part,
+                       prec, (_Float16*)ws, st);
+  else
+    hipLaunchKernelGGL(k_cast_fixup<unsigned char>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs,
+                       part, prec, (unsigned char*)ws, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_status_init(DevStatus* st, hipStream_t s) {

@@ -131,6 +131,7 @@ struct Builder {
     j.nparts = parts.second;
     j.tiles_r = (int)cdiv(rows, 64);
     j.tiles_c = (int)cdiv(j.ldq, 64);
+    j.final_part = -1;
     jobs.push_back(j);
     P.stats.cast_bytes += (double)rows * cols * (8.0 + esz);
     *ldq_out = j.ldq;
@@ -156,6 +157,9 @@ struct Builder {
     std::vector<CastJob> cj;
     std::vector<GemmProb> gp;
     const bool quant = prec == F16 || prec == E4M3;
+    // FP16 with scale_mode 0: one pass casts at scale 1 and records the max-abs
+    const bool single_pass = quant && prec == F16 && t.scale_mode == 0 && !single_wg;
+    if (single_pass) with_parts = false;
     for (const Node& nd : nodes) {
       GemmProb g{};
       g.c = off(nd.cr, nd.cc);
@@ -174,14 +178,36 @@ struct Builder {
       g.ynparts = py.second;
       if (quant) {
         int ldx = 0, ldy = 0;
+        // single pass: the tile partials of a job, then its final max-abs slot
+        auto own_parts = [&](CastJob& j) {
+          j.part0 = (int)part_cursor;
+          j.nparts = j.tiles_r * j.tiles_c;
+          j.final_part = j.part0 + j.nparts;
+          part_cursor += j.nparts + 1;
+          return std::make_pair(j.final_part, 1);
+        };
         g.x = add_cast(cj, prec, nd.xr, nd.xc, nd.m, nd.k, px, &ldx);
         g.ldx = ldx;
+        if (single_pass) {
+          px = own_parts(cj.back());
+          g.xpart0 = px.first;
+          g.xnparts = px.second;
+        }
         if (nd.lower) {
           g.y = g.x;
           g.ldy = ldx;
+          if (single_pass) {
+            g.ypart0 = px.first;
+            g.ynparts = px.second;
+          }
         } else {
           g.y = add_cast(cj, prec, nd.yr, nd.yc, nd.n, nd.k, py, &ldy);
           g.ldy = ldy;
+          if (single_pass) {
+            py = own_parts(cj.back());
+            g.ypart0 = py.first;
+            g.ynparts = py.second;
+          }
         }
       } else {
         g.x = off(nd.xr, nd.xc);
@@ -209,6 +235,7 @@ struct Builder {
       Launch L{Launch::CAST, prec};
       L.first = (int)P.casts.size();
       L.count = (int)cj.size();
+      L.a0 = single_pass ? 1 : 0;
       int wg = 0;
       for (auto& j : cj) {
         j.wg_start = wg;
@@ -217,6 +244,13 @@ struct Builder {
       L.total = wg;
       P.casts.insert(P.casts.end(), cj.begin(), cj.end());
       P.launches.push_back(L);
+      if (single_pass) {
+        Launch F{Launch::CASTFIX, prec};
+        F.first = L.first;
+        F.count = L.count;
+        F.total = L.count;
+        P.launches.push_back(F);
+      }
     }
     {
       Launch L{Launch::GEMM, prec};

@@ -12,9 +12,10 @@
 namespace mpc {
 
 struct Launch {
-  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV } kind;
+  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, CASTFIX } kind;
   int prec;
-  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k;
+                                          // CAST: a0 = 1 single-pass (scale 1 + max-abs)
   int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM:
                                           // leaf-inverse slot (TRSM: -1 = substitution)
   int tile = 128;                         // GEMM output tile (64 or 128)

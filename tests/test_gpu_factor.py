@@ -309,3 +309,24 @@ def test_cast_bitwise(M, ctx, prec, mode, shape, scale_pow):
         wb = np.vectorize(_e4m3_bits)(want).astype(np.uint8)
         np.testing.assert_array_equal(got[:rows, :cols], wb)
     assert np.all(got[:rows, cols:] == 0)
+
+
+@pytest.mark.parametrize("n,leaf", [(500, 64), (1100, 128)])
+def test_large_magnitude_block_scales(M, ctx, n, leaf):
+    """Entries far above the FP16 range: every quantized block needs a scale
+    above 1 (the single-pass cast re-casts those blocks); the result follows
+    the oracle's per-block scaling to the mixed-precision bars."""
+    print(f"[gpu] large-magnitude scales n={n}", flush=True)
+    A = spdgen.gen_spd(n, 1.3, 0.0, seed=n + 21) * 2.0 ** 44   # exact scaling
+    t = M.Tree(leaf=leaf, offdiag=[M.F16, M.F16, M.F32])
+    L, info = _gpu_factor(M, ctx, A, n, t)
+    assert info["status"] == M.OK, info
+    Le, st, _ = O.factor(A, tree=_otree(M, t))
+    L64, _, _ = O.factor(A, tree=O.Tree(leaf=leaf, offdiag=[O.F64]))
+    assert st == O.OK
+    assert np.max(np.abs(np.tril(L64[:n, :n], -1))) > 65504.0   # operands above the FP16 range
+    be_g, be_e = O.backward_error(A, L), O.backward_error(A, Le)
+    assert 0.5 <= be_g / be_e <= 2.0, (be_g, be_e)
+    d_ge = np.linalg.norm(np.tril(L[:n, :n]) - np.tril(Le[:n, :n]))
+    d_e64 = np.linalg.norm(np.tril(Le[:n, :n]) - np.tril(L64[:n, :n]))
+    assert d_ge <= 0.25 * d_e64, (d_ge, d_e64)
