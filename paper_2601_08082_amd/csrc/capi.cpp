@@ -45,6 +45,15 @@ struct mpchol_ctx_s {
   int64_t rbuf_count = 0;
   double* resw = nullptr;     // residual tile partials
   size_t resw_bytes = 0;
+  // load-distributed block solves: work items per order, helper partials, flags
+  std::map<int64_t, std::pair<int2*, int>> tsv_items;
+  double* tsv_p = nullptr;
+  size_t tsv_p_count = 0;
+  unsigned int* tsv_flag = nullptr;
+  size_t tsv_flag_count = 0;
+  double* tsv_x = nullptr;    // published solution blocks (n x kMaxRhs)
+  size_t tsv_x_count = 0;
+  unsigned int tsv_epoch = 0;
   double* npart = nullptr;    // norm partials (device)
   double* hnpart = nullptr;   // norm partials (pinned host)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -576,6 +585,10 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
   if (c->resw) (void)hipFree(c->resw);
+  for (auto& kv : c->tsv_items) (void)hipFree(kv.second.first);
+  if (c->tsv_p) (void)hipFree(c->tsv_p);
+  if (c->tsv_flag) (void)hipFree(c->tsv_flag);
+  if (c->tsv_x) (void)hipFree(c->tsv_x);
   if (c->npart) (void)hipFree(c->npart);
   if (c->hnpart) (void)hipHostFree(c->hnpart);
   if (c->dst) (void)hipFree(c->dst);
@@ -633,18 +646,72 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
   return status_from(*c->hst, info);
 }
 
+// Work items, helper partials and flags of the block solves of order n.
+static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
+  auto it = c->tsv_items.find(n);
+  if (it == c->tsv_items.end()) {
+    std::vector<int2> v;
+    trsv2_items(n, v);
+    int2* d = nullptr;
+    HIPCHK(hipMalloc((void**)&d, sizeof(int2) * v.size()));
+    HIPCHK(hipMemcpy(d, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice));
+    it = c->tsv_items.emplace(n, std::make_pair(d, (int)v.size())).first;
+  }
+  *items = it->second.first;
+  *nitems = it->second.second;
+  const size_t pc = trsv2_partial_doubles(n), fc = trsv2_flags(n);
+  if (pc > c->tsv_p_count) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->tsv_p) HIPCHK(hipFree(c->tsv_p));
+    c->tsv_p = nullptr;
+    c->tsv_p_count = 0;
+    HIPCHK(hipMalloc((void**)&c->tsv_p, sizeof(double) * pc));
+    c->tsv_p_count = pc;
+  }
+  const size_t xc = (size_t)n * kMaxRhs;
+  if (xc > c->tsv_x_count) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->tsv_x) HIPCHK(hipFree(c->tsv_x));
+    c->tsv_x = nullptr;
+    c->tsv_x_count = 0;
+    HIPCHK(hipMalloc((void**)&c->tsv_x, sizeof(double) * xc));
+    c->tsv_x_count = xc;
+  }
+  if (fc > c->tsv_flag_count || c->tsv_epoch > 0xFFFFFF00u) {
+    // flags only ever hold epochs of earlier calls (or 0): zero them once here
+    HIPCHK(hipDeviceSynchronize());
+    if (c->tsv_flag) HIPCHK(hipFree(c->tsv_flag));
+    c->tsv_flag = nullptr;
+    c->tsv_flag_count = 0;
+    HIPCHK(hipMalloc((void**)&c->tsv_flag, sizeof(unsigned int) * fc));
+    HIPCHK(hipMemset(c->tsv_flag, 0, sizeof(unsigned int) * fc));
+    HIPCHK(hipDeviceSynchronize());
+    c->tsv_flag_count = fc;
+    c->tsv_epoch = 0;
+  }
+  return 0;
+}
+
 // X <- L^-T L^-1 X for up to kMaxRhs columns at a time.
 static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
   const double lbytes = (double)n * (n + 1) / 2 * 8.0;
+  int2* items = nullptr;
+  int nitems = 0;
+  int r = ensure_trsv(c, n, &items, &nitems);
+  if (r) return r;
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     HIPCHK(launch_ticket_reset(c->dst, s));
     int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 0, s));
+    HIPCHK(launch_trsv2(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, items, nitems, c->tsv_p,
+                        c->tsv_flag,
+                        ++c->tsv_epoch, c->dst, 0, s));
     prof_end(c, pk, s);
     pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->dst, 2, s));
+    HIPCHK(launch_trsv2(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, items, nitems, c->tsv_p,
+                        c->tsv_flag,
+                        ++c->tsv_epoch, c->dst, 2, s));
     prof_end(c, pk, s);
   }
   return 0;

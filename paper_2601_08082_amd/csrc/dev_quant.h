@@ -96,13 +96,12 @@ __device__ inline double cast_core(const double* __restrict__ Lm, int64_t ldl, c
     tile[rr][cc] = q;
   }
   if (want_max) {
-    red[threadIdx.x] = m;
+    // wave maximum by butterfly, then the four waves through LDS (one barrier)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
-      __syncthreads();
-    }
-    m = red[0];
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   } else {
     __syncthreads();
   }

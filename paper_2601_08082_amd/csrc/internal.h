@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mpc {
 
 enum Prec : int32_t { E4M3 = 0, F16 = 1, F32 = 2, F64 = 3 };
@@ -94,11 +96,20 @@ hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64
                             int64_t c0, int k, hipStream_t s);
 
 // Solve / refinement kernels.
-hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs,
-                       double* X, int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s);
 // R = B - A X (A symmetric, lower stored, read once); work holds
 // residual_work_bytes(n, nrhs) bytes of tile partials.
 size_t residual_work_bytes(int64_t n, int nrhs);
+// Load-distributed block solve: ticketed diagonal and helper items (the list
+// from trsv2_items), helper partial sums in P (trsv2_partial_doubles(n)) with
+// epoch-tagged flags (trsv2_flags(n) words, zero before first use), and XP
+// (n x nrhs doubles, ld n) for the published solution blocks.
+int trsv2_items(int64_t n, std::vector<int2>& items);
+size_t trsv2_partial_doubles(int64_t n);
+size_t trsv2_flags(int64_t n);
+hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
+                        int64_t ldx, double* XP, const int2* items, int nitems, double* P,
+                        unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
+                        hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
                            double* work, hipStream_t s);

@@ -1,10 +1,13 @@
 // Solve and FP64-residual iterative refinement kernels:
-//   - blocked triangular solves L y = b and L^T x = y, one workgroup per
-//     64-row block, blocks handed out by a ticket counter so that a block only
-//     waits (bounded spin) on blocks that are already running;
+//   - blocked triangular solves L y = b and L^T x = y over 64-row blocks:
+//     ticketed diagonal and helper work items (see k_trsv2), every wait a
+//     bounded spin on an item with a smaller ticket;
 //   - the FP64 residual R = B - A X with A symmetric and only its lower
 //     triangle read;
 //   - X += D with per-column max-abs of D and X for the stopping rule.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 namespace mpc {
@@ -30,16 +33,34 @@ __device__ inline double bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Wait until *done > k.  Returns false (and flags st->wait_timeout) when the
-// bounded spin gives up, so that every wave always exits.  The spin uses
-// relaxed loads and one acquire fence at the end: an acquire per poll would
-// invalidate the L2 of the polling die on every iteration.
-__device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* st) {
+// Load-distributed block solve.  Work items, handed out by ticket in a
+// dependency-safe order (every wait is on an item with a smaller ticket):
+//   D(s)    diagonal block s (in solve order): folds in the helper sums of the
+//           column chunks c <= s / CW - 2, then itself the blocks K from
+//           CW (s / CW) - CW up to s - 1 as they are published (so the last
+//           dependency costs one hop), then solves its diagonal block (one
+//           wave, lane = row) and publishes x_s;
+//   T(s, c) helper: the sum over the CW blocks K of chunk c of L(s, K) x_K
+//           (or L(K, s)^T x_K), written to P[s][c] and flagged with this
+//           call's epoch.
+// A block row thus reads at most 2 CW - 1 of its blocks itself, and the rest
+// of the row is read in parallel by helpers, instead of one workgroup reading
+// the whole row.  Partial sums are added in chunk order: deterministic.
+// Solved blocks are published by agent-scope atomic stores into a copy that
+// was filled with a sentinel before the launch; readers poll the values
+// themselves (each written once), so a hop costs one coherent round trip and
+// no release/acquire cache maintenance.
+constexpr int CW = 8;
+// fill value of the published copies (a signalling-NaN payload that no
+// arithmetic produces)
+constexpr unsigned long long kSentinel = 0x7FF4D5A1B2C3E4F5ull;
+
+__device__ inline bool wait_flag(unsigned int* f, unsigned int epoch, DevStatus* st) {
   __shared__ int ok;
   if (threadIdx.x == 0) {
     long spins = 0;
     ok = 1;
-    while (atomic_load_rlx(done) <= k) {
+    while (atomic_load_rlx(f) != epoch) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) {
         atomicOr(&st->wait_timeout, 1u);
@@ -55,47 +76,61 @@ __device__ inline bool wait_done(unsigned int* done, unsigned int k, DevStatus* 
   return r;
 }
 
-// trans = 0: X <- L^{-1} X (forward).  trans = 1: X <- L^{-T} X (backward).
-// ticket[slot] hands out block order, ticket[slot + 1] counts finished blocks.
-// A workgroup stages its diagonal block first, then folds in every earlier
-// block's contribution as soon as that block is published, then solves its
-// diagonal block with one wave (lane = row, readlane broadcasts).  NR is the
-// compile-time number of right-hand sides handled (>= nrhs).
 template <int NR>
-__global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restrict__ Lm,
-                                              int64_t ldl, int64_t n, int nrhs, double* X,
-                                              int64_t ldx, DevStatus* st, int slot) {
-  __shared__ double blk[NB][NB + 1];   // staged off-diagonal block, blk[col][row]
-  __shared__ double dg[NB][NB + 1];    // diagonal block, dg[col][row]
-  __shared__ double xs[NB][NR];        // solved block of another workgroup
+__global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restrict__ Lm,
+                                               int64_t ldl, int64_t n, int nrhs, double* X,
+                                               int64_t ldx, double* XP,
+                                               const int2* __restrict__ items, double* P,
+                                               unsigned int* pflag, unsigned int epoch,
+                                               DevStatus* st, int slot) {
+  __shared__ double blk[NB][NB + 1];
+  __shared__ double dg[NB][NB + 1];
+  __shared__ double xs[NB][NR];
   __shared__ double acc[4][NB][NR];
   __shared__ unsigned int my_ticket;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int nblk = (int)((n + NB - 1) / NB);
+  const int nch = nblk / CW + 1;
   if (tid == 0) my_ticket = atomicAdd(&st->ticket[slot], 1u);
   __syncthreads();
-  const int t = (int)my_ticket;
-  unsigned int* done = &st->ticket[slot + 1];
-  const int J = trans ? nblk - 1 - t : t;
+  const int2 it = items[my_ticket];           // x = s (solve order), y = chunk (-1: diagonal item)
+  const int sidx = it.x, chunk = it.y;
+  const int J = trans ? nblk - 1 - sidx : sidx;
   const int64_t j0 = (int64_t)J * NB;
   const int nj = (int)min((int64_t)NB, n - j0);
-  const int r = tid & 63, g = tid >> 6;
-
-  // diagonal block, staged before any waiting
+  const bool diag = chunk < 0;
+  if (diag) {
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; u++) {
-    const int idx = tid + 256 * u;
-    const int i = idx & 63, q = idx >> 6;
-    const double v = Lm[(j0 + min(i, nj - 1)) + (j0 + min(q, nj - 1)) * ldl];
-    dg[q][i] = (i < nj && q < nj && i >= q) ? v : 0.0;
+    for (int u = 0; u < NB * NB / 256; u++) {
+      const int idx = tid + 256 * u;
+      const int i = idx & 63, q = idx >> 6;
+      const double v = Lm[(j0 + min(i, nj - 1)) + (j0 + min(q, nj - 1)) * ldl];
+      dg[q][i] = (i < nj && q < nj && i >= q) ? v : 0.0;
+    }
   }
-
   double part[NR];
 #pragma unroll
   for (int c = 0; c < NR; c++) part[c] = 0.0;
-
-  for (int s = 0; s < t; s++) {
-    const int K = trans ? nblk - 1 - s : s;
+  int k_begin, k_end;
+  if (diag) {
+    // helper sums of the chunks before the window, in chunk order
+    const int hc = sidx / CW - 1;      // chunks 0 .. hc - 1
+    for (int c2 = 0; c2 < hc; c2++) {
+      if (!wait_flag(&pflag[(int64_t)sidx * nch + c2], epoch, st)) return;
+      if (g == 0) {
+        const double* pp = P + ((int64_t)sidx * nch + c2) * NB * NR;
+#pragma unroll
+        for (int c = 0; c < NR; c++) part[c] += coherent_load(&pp[r * NR + c]);
+      }
+    }
+    k_begin = max(0, CW * (sidx / CW) - CW);
+    k_end = sidx;
+  } else {
+    k_begin = chunk * CW;
+    k_end = chunk * CW + CW;
+  }
+  for (int sk = k_begin; sk < k_end; sk++) {
+    const int K = trans ? nblk - 1 - sk : sk;
     const int64_t k0 = (int64_t)K * NB;
     const int nk = (int)min((int64_t)NB, n - k0);
     double tmp[NB * NB / 256];
@@ -111,37 +146,65 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
       const bool in = trans ? (i < nk && q < nj) : (i < nj && q < nk);
       tmp[u] = in ? v : 0.0;
     }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; u++) {
       const int idx = tid + 256 * u;
       blk[idx >> 6][idx & 63] = tmp[u];
     }
-    if (!wait_done(done, (unsigned)s, st)) return;
+    // x_K from its published copy: every value is written once per call over
+    // a sentinel, so a value that is not the sentinel is final
     for (int idx = tid; idx < NB * NR; idx += 256) {
       const int i = idx % NB, c = idx / NB;
-      xs[i][c] = (i < nk && c < nrhs) ? coherent_load(&X[(k0 + i) + (int64_t)c * ldx]) : 0.0;
+      double v = 0.0;
+      if (i < nk && c < nrhs) {
+        unsigned long long* p =
+            reinterpret_cast<unsigned long long*>(XP + (k0 + i) + (int64_t)c * n);
+        unsigned long long b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (b == kSentinel && spins < kSpinLimit) {
+          __builtin_amdgcn_s_sleep(1);
+          ++spins;
+          b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (b == kSentinel) atomicOr(&st->wait_timeout, 1u);
+        v = b == kSentinel ? 0.0 : __longlong_as_double((long long)b);
+      }
+      xs[i][c] = v;
     }
     __syncthreads();
     if (!trans) {
-      // part[r] += sum_{q = g mod 4} L(j0 + r, k0 + q) x(k0 + q)
       for (int q = g; q < NB; q += 4) {
         const double l = blk[q][r];
 #pragma unroll
         for (int c = 0; c < NR; c++) part[c] += l * xs[q][c];
       }
     } else {
-      // part[r] += sum_{i = g mod 4} L(k0 + i, j0 + r) x(k0 + i)
       for (int i = g; i < NB; i += 4) {
         const double l = blk[r][i];
 #pragma unroll
         for (int c = 0; c < NR; c++) part[c] += l * xs[i][c];
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 #pragma unroll
   for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
   __syncthreads();
+  if (!diag) {
+    double* pp = P + ((int64_t)sidx * nch + chunk) * NB * NR;
+    for (int idx = tid; idx < NB * NR; idx += 256) {
+      const int i = idx / NR, c = idx % NR;
+      pp[idx] = (acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&pflag[(int64_t)sidx * nch + chunk], epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   if (tid < 64) {
     const int i = tid;
     double v[NR];
@@ -150,10 +213,10 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
       const double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * ldx] : 0.0;
       v[c] = b - ((acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]));
     }
-    const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;   // lane i: 1 / L(i, i)
+    const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;
     if (!trans) {
       for (int j = 0; j < nj; j++) {
-        const double lij = dg[j][i];             // L(i, j)
+        const double lij = dg[j][i];
         const double ij = bcast(inv, j);
 #pragma unroll
         for (int c = 0; c < NR; c++) {
@@ -164,7 +227,7 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
       }
     } else {
       for (int j = nj - 1; j >= 0; j--) {
-        const double lji = dg[i][j];             // L(j, i) for i < j
+        const double lji = dg[i][j];
         const double ij = bcast(inv, j);
 #pragma unroll
         for (int c = 0; c < NR; c++) {
@@ -176,14 +239,73 @@ __global__ __launch_bounds__(256) void k_trsv(int trans, const double* __restric
     }
 #pragma unroll
     for (int c = 0; c < NR; c++)
-      if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * ldx] = v[c];
+      if (c < nrhs && i < nj) {
+        X[(j0 + i) + (int64_t)c * ldx] = v[c];
+        // the published copy, coherent across the dies without a fence
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + i) + (int64_t)c * n),
+                           (unsigned long long)__double_as_longlong(v[c]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
   }
-  __syncthreads();
-  // one agent-scope release (L2 write-back) publishes every wave's stores
-  if (tid == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_fill_sentinel(unsigned long long* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = kSentinel;
+}
+
+int trsv2_items(int64_t n, std::vector<int2>& items) {
+  const int nblk = (int)((n + NB - 1) / NB);
+  items.clear();
+  for (int s = 0; s < nblk; s++) {
+    items.push_back(make_int2(s, -1));
+    if ((s + 1) % CW == 0) {
+      const int c = s / CW;
+      for (int s2 = (c + 2) * CW; s2 < nblk; s2++) items.push_back(make_int2(s2, c));
+    }
   }
+  return nblk;
+}
+
+size_t trsv2_partial_doubles(int64_t n) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  return (size_t)(nblk * (nblk / CW + 1)) * NB * MAXRHS;
+}
+size_t trsv2_flags(int64_t n) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  return (size_t)(nblk * (nblk / CW + 1));
+}
+
+hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
+                        int64_t ldx, double* XP, const int2* items, int nitems, double* P,
+                        unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
+                        hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (nrhs > MAXRHS || (ticket_slot != 0 && ticket_slot != 2)) return hipErrorInvalidValue;
+  {
+    const int64_t cnt = n * nrhs;
+    const unsigned gx = (unsigned)std::min<int64_t>((cnt + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_sentinel, dim3(gx), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(XP), cnt);
+  }
+  dim3 g(nitems), b(256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_trsv2<1>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+                       epoch, st, ticket_slot);
+  else if (nrhs <= 2)
+    hipLaunchKernelGGL(k_trsv2<2>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+                       epoch, st, ticket_slot);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL(k_trsv2<4>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+                       epoch, st, ticket_slot);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL(k_trsv2<8>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+                       epoch, st, ticket_slot);
+  else
+    hipLaunchKernelGGL(k_trsv2<16>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+                       epoch, st, ticket_slot);
+  return hipGetLastError();
 }
 
 // R = B - A X, A symmetric with its lower triangle stored, every stored
@@ -359,24 +481,6 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t n, int nrhs, const do
     dst[i + c * ldd] = src[i + c * lds];
 }
 
-hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
-                       int64_t ldx, DevStatus* st, int ticket_slot, hipStream_t s) {
-  if (n <= 0 || nrhs <= 0) return hipSuccess;
-  if (nrhs > MAXRHS || (ticket_slot != 0 && ticket_slot != 2)) return hipErrorInvalidValue;
-  int nblk = (int)((n + NB - 1) / NB);
-  dim3 g(nblk), b(256);
-  if (nrhs == 1)
-    hipLaunchKernelGGL(k_trsv<1>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
-  else if (nrhs <= 2)
-    hipLaunchKernelGGL(k_trsv<2>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
-  else if (nrhs <= 4)
-    hipLaunchKernelGGL(k_trsv<4>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
-  else if (nrhs <= 8)
-    hipLaunchKernelGGL(k_trsv<8>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
-  else
-    hipLaunchKernelGGL(k_trsv<16>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, st, ticket_slot);
-  return hipGetLastError();
-}
 
 static int resid_nr(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
 
