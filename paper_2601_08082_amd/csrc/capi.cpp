@@ -108,6 +108,7 @@ static int launch_kind(const Launch& L) {
     case Launch::POTRF: return MPCHOL_PROF_POTRF;
     case Launch::TRINV: return MPCHOL_PROF_TRINV;
     case Launch::CASTFIX: return MPCHOL_PROF_MAXABS;
+    case Launch::INVJOIN: return MPCHOL_PROF_TRINV;
     default: return MPCHOL_PROF_TRSM;
   }
 }
@@ -170,6 +171,8 @@ static double launch_work(const Plan& P, const Launch& L) {
     }
   } else if (L.kind == Launch::CASTFIX) {
     for (int i = 0; i < L.count; i++) w += (double)P.casts[L.first + i].nparts * 8.0;
+  } else if (L.kind == Launch::INVJOIN) {
+    w = 2.0 * (double)(L.a1 - L.a2) * L.a2 * L.a1;   // the two products
   } else if (L.kind == Launch::POTRF || L.kind == Launch::TRINV) {
     w = (double)L.a1 * L.a1 * L.a1 / 3.0;
   } else {
@@ -244,13 +247,19 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
       case Launch::TRSM:
         if (Lc.first >= 0)
           e = launch_trsm_inv(L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3,
-                              c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
+                              c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
         else
           e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
         break;
       case Launch::TRINV:
         e = launch_trinv(L, ldl, Lc.a0, (int)Lc.a1,
-                         c->inv + (size_t)Lc.first * kKernelLeaf * kKernelLeaf, s);
+                         c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
+        break;
+      case Launch::INVJOIN:
+        // scratch: the slot after the last one
+        e = launch_inv_join(L, ldl, Lc.a0, (int)Lc.a1, (int)Lc.a2,
+                            c->inv + (size_t)Lc.first * kInvLd * kInvLd, kInvLd,
+                            c->inv + (size_t)P.ninv * kInvLd * kInvLd, s);
         break;
       case Launch::MAXABS:
         e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
@@ -628,7 +637,7 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
     if (c->inv) HIPCHK(hipFree(c->inv));
     c->inv = nullptr;
     c->ninv = 0;
-    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kKernelLeaf * kKernelLeaf * (size_t)P->ninv));
+    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kInvLd * kInvLd * (size_t)(P->ninv + 1)));
     c->ninv = P->ninv;
   }
   if (info) HIPCHK(hipEventRecord(c->ev0, s));
@@ -913,7 +922,7 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         build_plan(P, n_host[i], ldl_host[i], &t, true, tile);
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
-          if (L.kind == Launch::TRINV || L.kind == Launch::CASTFIX ||
+          if (L.kind == Launch::TRINV || L.kind == Launch::CASTFIX || L.kind == Launch::INVJOIN ||
               (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0)) {
             free_batch(c);
             return MPCHOL_HIP_ERROR;   // workgroup-level plans never use leaf inverses

@@ -272,8 +272,9 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
 }
 
 // ---------------------------------------------------------------- inverse
-// Y = L^{-1} of the FP64 leaf L = A(i0:i0+m, i0:i0+m), m <= 128, into Y
-// (column-major, ld KL, zero above the diagonal and outside m x m).  L and Y
+// Y = L^{-1} of the FP64 leaf L = A(i0:i0+m, i0:i0+m), m <= 128, into the
+// 128 x 128 block at Y (column-major, ld ldy, zero above the diagonal and
+// outside m x m).  L and Y
 // live in LDS as 16 x 16 lower blocks (row-major, padded rows).  Diagonal
 // blocks: column-by-column substitution with true division; off-diagonal
 // blocks by block columns, Y_ij = -Y_ii (sum_{k=j}^{i-1} L_ik Y_kj), with
@@ -292,7 +293,7 @@ __device__ inline void wave_lds_order() {
 }
 
 __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, int64_t i0, int m,
-                                  double* __restrict__ Y, char* lds) {
+                                  double* __restrict__ Y, int ldy, char* lds) {
   double* l = reinterpret_cast<double*>(lds);   // L blocks
   double* y = l + inv_blocks() * IB * IBP;      // Y blocks
   __syncthreads();
@@ -369,57 +370,67 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
 #pragma unroll 8
   for (int r = 0; r < KL * KL / 256; r++) {
     const int idx = tid + 256 * r;
-    const int i = idx % KL, j = idx / KL;   // Y(i, j), column-major, ld KL
+    const int i = idx % KL, j = idx / KL;   // Y(i, j), column-major, ld ldy
     double v = 0.0;
     if (i < m && j < m && i >= j) v = y[iblk(i >> 4, j >> 4) + (i & 15) * IBP + (j & 15)];
-    Y[i + j * KL] = v;
+    Y[i + (int64_t)j * ldy] = v;
   }
 }
 
-// Rows [r0 + 16 rblk, +16) of B <- B L^{-T} = B Y^T with Y = L^{-1} from
-// trinv_body: X(i, j) = sum_{l <= j} B(i, l) Y(j, l), FP64 MFMA.  Wave w
-// computes column blocks w and 7 - w; every wave reads the whole row block of
+// Rows [r0 + 16 rblk, +16) of B <- B L^{-T} = B Y^T with Y = L^{-1} (k <=
+// 16 NCB, column-major, ld ldy, lower): X(i, j) = sum_{l <= j} B(i, l) Y(j, l),
+// FP64 MFMA.  The 16-column blocks are dealt to the waves in mirrored pairs
+// (w, NCB - 1 - w, ...) for balance; every wave reads the whole row block of
 // B before any wave writes (in place).
+template <int NCB>
 __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64_t r0, int64_t m,
-                                     int64_t c0, int k, const double* __restrict__ Y, int rblk) {
+                                     int64_t c0, int k, const double* __restrict__ Y, int ldy,
+                                     int rblk) {
+  constexpr int PER = NCB / 4;                 // column blocks per wave
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t rb = r0 + (int64_t)rblk * IB;
   const int rows = (int)min((int64_t)IB, r0 + m - rb);
   const int nb = (k + IB - 1) / IB;
   double* B = Lm + rb + c0 * ldl;
-  const int cbs[2] = {wave, NIB - 1 - wave};
-  const int lbmax = max(cbs[0] < nb ? cbs[0] : -1, cbs[1] < nb ? cbs[1] : -1);
+  int cbs[PER];
+#pragma unroll
+  for (int h = 0; h < PER; h++) cbs[h] = (h & 1) ? 4 * (h + 1) - 1 - wave : 4 * h + wave;
+  int lbmax = -1;
+#pragma unroll
+  for (int h = 0; h < PER; h++) lbmax = max(lbmax, cbs[h] < nb ? cbs[h] : -1);
   // A fragments: a[lb][q] = B(lane%16, 16 lb + 4 q + lane/16)
-  double a[NIB][4];
+  double a[NCB][4];
   const int ri = min(lane & 15, rows - 1);
 #pragma unroll
-  for (int lb = 0; lb < NIB; lb++)
+  for (int lb = 0; lb < NCB; lb++)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       const int col = 16 * lb + 4 * q + (lane >> 4);
       const double v = B[ri + (int64_t)min(col, k - 1) * ldl];
       a[lb][q] = (lb <= lbmax && col < k && (lane & 15) < rows) ? v : 0.0;
     }
-  f64x4 acc[2];
+  f64x4 acc[PER];
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
+  for (int h = 0; h < PER; h++) {
     acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int cb = cbs[h];
     if (cb >= nb) continue;
 #pragma unroll
-    for (int lb = 0; lb < NIB; lb++) {
-      if (lb > cb) break;
+    for (int lb = 0; lb < NCB; lb++) {
+      if (lb <= cb) {   // wave-uniform
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        // B operand (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk)
-        const double bv = Y[(16 * cb + (lane & 15)) + (16 * lb + 4 * q + (lane >> 4)) * KL];
-        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], bv, acc[h], 0, 0, 0);
+        for (int q = 0; q < 4; q++) {
+          // B operand (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk)
+          const double bv =
+              Y[(16 * cb + (lane & 15)) + (int64_t)(16 * lb + 4 * q + (lane >> 4)) * ldy];
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], bv, acc[h], 0, 0, 0);
+        }
       }
     }
   }
   __syncthreads();   // every wave has consumed its reads of B
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
+  for (int h = 0; h < PER; h++) {
     const int cb = cbs[h];
     if (cb >= nb) continue;
     const int col = 16 * cb + (lane & 15);
@@ -428,6 +439,38 @@ __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64
       const int row = (lane >> 4) + 4 * r;
       if (row < rows && col < k) B[row + (int64_t)col * ldl] = acc[h][r];
     }
+  }
+}
+
+// C(M x N) = alpha A(M x K) B(K x N), all column-major FP64, M, N, K <= 128:
+// one wave per 16 x 16 output tile (blockIdx.x = tile), FP64 MFMA.  Used to
+// join two leaf inverses into the inverse of their parent block.
+__device__ inline void small_gemm_tile(double* __restrict__ C, int ldc, const double* __restrict__ A,
+                                       int64_t lda, const double* __restrict__ Bm, int ldb, int M,
+                                       int N, int K, double alpha) {
+  const int lane = threadIdx.x & 63;
+  const int tiles_m = (M + 15) / 16;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int i = 16 * tm + (lane & 15), j = 16 * tn + (lane & 15);
+  // all fragments in flight first (K <= 128: 32 of each), then the MFMA chain
+  double av[KL / 4], bv[KL / 4];
+  const int ic = min(i, M - 1), jc = min(j, N - 1);
+#pragma unroll
+  for (int q = 0; q < KL / 4; q++) {
+    const int kk = 4 * q + (lane >> 4), kc = min(kk, K - 1);
+    const double a = A[ic + (int64_t)kc * lda];
+    const double b = Bm[kc + (int64_t)jc * ldb];
+    av[q] = (i < M && kk < K) ? a : 0.0;
+    bv[q] = (j < N && kk < K) ? b : 0.0;
+  }
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < KL / 4; q++)
+    if (4 * q < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int row = 16 * tm + (lane >> 4) + 4 * r, col = 16 * tn + (lane & 15);
+    if (row < M && col < N) C[row + (int64_t)col * ldc] = alpha * acc[r];
   }
 }
 

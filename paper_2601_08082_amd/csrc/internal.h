@@ -87,11 +87,16 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
                        int scale_mode, DevStatus* st, hipStream_t s);
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m,
                              DevStatus* st, hipStream_t s);
-// FP64 leaf inverse (Y: KL x KL, column-major, ld KL) and the TRSM through it.
-hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y,
+// FP64 leaf inverses: of a kernel leaf (m <= KL) into a KL x KL block of Y
+// (ld ldy); the join of two consecutive leaf inverses into their parent's
+// (Y21 = -Y2 L21 Y1, T: KL x KL scratch); and the TRSM through an inverse of
+// order k <= 2 KL.
+hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y, int ldy,
                         hipStream_t s);
+hipError_t launch_inv_join(const double* Lm, int64_t ldl, int64_t i0, int m, int m1, double* Y,
+                           int ldy, double* T, hipStream_t s);
 hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
-                           const double* Y, hipStream_t s);
+                           const double* Y, int ldy, hipStream_t s);
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,
                             int64_t c0, int k, hipStream_t s);
 

@@ -42,31 +42,55 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(double* __restrict__ Lm, int6
 }
 
 __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Lm, int64_t ldl,
-                                               int64_t i0, int m, double* __restrict__ Y) {
+                                               int64_t i0, int m, double* __restrict__ Y, int ldy) {
   __shared__ __attribute__((aligned(16))) char pool[trinv_lds_bytes()];
-  trinv_body(Lm, ldl, i0, m, Y, pool);
+  trinv_body(Lm, ldl, i0, m, Y, ldy, pool);
 }
 
+template <int NCB>
 __global__ __launch_bounds__(256) void k_trsm_inv(double* __restrict__ Lm, int64_t ldl, int64_t r0,
                                                   int64_t m, int64_t c0, int k,
-                                                  const double* __restrict__ Y) {
-  trsm_inv_rows(Lm, ldl, r0, m, c0, k, Y, blockIdx.x);
+                                                  const double* __restrict__ Y, int ldy) {
+  trsm_inv_rows<NCB>(Lm, ldl, r0, m, c0, k, Y, ldy, blockIdx.x);
 }
 
-hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y,
+__global__ __launch_bounds__(64) void k_small_gemm(double* __restrict__ C, int ldc,
+                                                   const double* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ B, int ldb, int M,
+                                                   int N, int K, double alpha) {
+  small_gemm_tile(C, ldc, A, lda, B, ldb, M, N, K, alpha);
+}
+
+hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y, int ldy,
                         hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  if (m > KL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trinv, dim3(1), dim3(256), 0, s, Lm, ldl, i0, m, Y);
+  if (m > KL || ldy < KL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trinv, dim3(1), dim3(256), 0, s, Lm, ldl, i0, m, Y, ldy);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
-                           const double* Y, hipStream_t s) {
+                           const double* Y, int ldy, hipStream_t s) {
   if (m <= 0 || k <= 0) return hipSuccess;
-  if (k > KL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trsm_inv, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, Lm, ldl, r0, m,
-                     c0, k, Y);
+  if (k > 2 * KL || ldy < k) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((m + 15) / 16));
+  if (k <= KL)
+    hipLaunchKernelGGL(k_trsm_inv<8>, g, dim3(256), 0, s, Lm, ldl, r0, m, c0, k, Y, ldy);
+  else
+    hipLaunchKernelGGL(k_trsm_inv<16>, g, dim3(256), 0, s, Lm, ldl, r0, m, c0, k, Y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_join(const double* Lm, int64_t ldl, int64_t i0, int m, int m1, double* Y,
+                           int ldy, double* T, hipStream_t s) {
+  // Y = [Y1 0; Y21 Y2] with Y21 = -Y2 (L21 Y1), L21 = L(i0+m1 : i0+m, i0 : i0+m1)
+  const int m2 = m - m1;
+  if (m1 <= 0 || m2 <= 0 || m1 > KL || m2 > KL) return hipErrorInvalidValue;
+  const double* L21 = Lm + (i0 + m1) + i0 * ldl;
+  const dim3 g((unsigned)(((m2 + 15) / 16) * ((m1 + 15) / 16)));
+  hipLaunchKernelGGL(k_small_gemm, g, dim3(64), 0, s, T, KL, L21, ldl, Y, ldy, m2, m1, m1, 1.0);
+  hipLaunchKernelGGL(k_small_gemm, g, dim3(64), 0, s, Y + m1, ldy, Y + m1 + (int64_t)m1 * ldy,
+                     (int64_t)ldy, T, KL, m2, m1, m2, -1.0);
   return hipGetLastError();
 }
 

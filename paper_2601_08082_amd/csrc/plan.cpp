@@ -74,7 +74,8 @@ struct Builder {
   int64_t ldl;
   bool single_wg = false;
   int tile_force = 0;
-  std::map<int64_t, std::pair<int, int64_t>> inv_slot;   // kernel-leaf origin -> (slot, order)
+  // (origin, order) of a diagonal block with an inverse -> (slot, element offset)
+  std::map<std::pair<int64_t, int64_t>, std::pair<int, int64_t>> inv_slot;
 
   // FP64 leaves of the single-matrix path solve their TRSMs through the inverse
   bool use_inverse() const { return !single_wg && t.leaf_prec == F64 && t.leaf_trsm == 0; }
@@ -298,7 +299,9 @@ struct Builder {
     return std::max<int64_t>(1, std::min(h, m - 1));
   }
 
-  void leaf_potrf(int64_t i0, int64_t m) {
+  // slot >= 0: the inverse goes into that slot at element offset off (the
+  // second half of a joined 256-leaf); otherwise a new slot
+  void leaf_potrf(int64_t i0, int64_t m, int slot = -1, int64_t off = 0) {
     if (m <= 0) return;
     if (m <= kKernelLeaf) {
       Launch L{Launch::POTRF, t.leaf_prec};
@@ -310,32 +313,48 @@ struct Builder {
         Launch I{Launch::TRINV, F64};
         I.a0 = i0;
         I.a1 = m;
-        I.first = P.ninv++;
-        inv_slot[i0] = {I.first, m};
+        I.first = slot >= 0 ? slot : P.ninv++;
+        I.off = slot >= 0 ? off : 0;
+        inv_slot[{i0, m}] = {I.first, I.off};
         P.launches.push_back(I);
       }
       return;
     }
     int64_t m1 = leaf_split(m), m2 = m - m1;
-    leaf_potrf(i0, m1);
+    // a leaf of two kernel leaves gets one inverse: the halves' inverses joined
+    const bool join = use_inverse() && m <= kInvLd;
+    const int js = join ? P.ninv++ : -1;
+    leaf_potrf(i0, m1, js, 0);
     leaf_trsm(i0 + m1, m2, i0, m1);
     gemm_one(Node{i0 + m1, i0 + m1, (int)m2, (int)m2, i0 + m1, i0, i0 + m1, i0, (int)m1, 1,
                   t.leaf_prec},
              false);
-    leaf_potrf(i0 + m1, m2);
+    leaf_potrf(i0 + m1, m2, js, m1 + m1 * (int64_t)kInvLd);
+    if (join) {
+      Launch J{Launch::INVJOIN, F64};
+      J.a0 = i0;
+      J.a1 = m;
+      J.a2 = m1;
+      J.first = js;
+      P.launches.push_back(J);
+      inv_slot[{i0, m}] = {js, 0};
+    }
   }
 
   void leaf_trsm(int64_t r0, int64_t m, int64_t c0, int64_t k) {
     if (m <= 0 || k <= 0) return;
-    if (k <= kKernelLeaf) {
+    auto it = use_inverse() ? inv_slot.find({c0, k}) : inv_slot.end();
+    if (it != inv_slot.end() || k <= kKernelLeaf) {
       Launch L{Launch::TRSM, t.leaf_prec};
       L.a0 = r0;
       L.a1 = m;
       L.a2 = c0;
       L.a3 = k;
       L.first = -1;
-      auto it = inv_slot.find(c0);
-      if (use_inverse() && it != inv_slot.end() && it->second.second == k) L.first = it->second.first;
+      if (it != inv_slot.end()) {
+        L.first = it->second.first;
+        L.off = it->second.second;
+      }
       P.launches.push_back(L);
       P.stats.leaf_flops += (double)m * k * k;
       return;

@@ -12,12 +12,14 @@
 namespace mpc {
 
 struct Launch {
-  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, CASTFIX } kind;
+  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, CASTFIX, INVJOIN } kind;
   int prec;
   int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k;
                                           // CAST: a0 = 1 single-pass (scale 1 + max-abs)
-  int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM:
-                                          // leaf-inverse slot (TRSM: -1 = substitution)
+  int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM /
+                                          // INVJOIN: leaf-inverse slot (TRSM: -1 = substitution)
+  int64_t off = 0;                        // TRINV / TRSM: element offset in the slot
+                                          // (INVJOIN: a0 = i0, a1 = m, a2 = m1)
   int tile = 128;                         // GEMM output tile (64 or 128)
 };
 
@@ -27,6 +29,8 @@ struct PlanStats {
   double cast_bytes = 0;           // algorithmic bytes of quantize casts
   int64_t n_launch = 0;
 };
+
+constexpr int kInvLd = 2 * kKernelLeaf;   // leaf-inverse slot: up to two joined kernel leaves
 
 struct Plan {
   int64_t n = 0, ldl = 0;
@@ -38,7 +42,7 @@ struct Plan {
   std::vector<GemmProb> gemms;
   size_t ws_bytes = 0;     // quantized-operand workspace needed
   int64_t parts = 0;       // maxabs partial slots needed
-  int ninv = 0;            // leaf-inverse slots (KL x KL doubles each)
+  int ninv = 0;            // leaf-inverse slots (kInvLd x kInvLd doubles each)
   PlanStats stats;
   // device copies of the descriptor arrays
   MaxabsJob* d_maxabs = nullptr;
