@@ -91,41 +91,40 @@ __device__ inline void potrf_leaf_body(double* __restrict__ Lm, int64_t ldl, int
   }
   __syncthreads();
   for (int p = 0; p < mp; p += PW) {
-    if (wave == 0) {
-      // panel elimination in registers: lane owns rows ra = lane and rb = lane + 64;
-      // the panel's own rows p..p+15 all live in the same half (PW divides 64)
-      const int ra = lane, rb = lane + 64;
-      const bool lo = p < 64;
-      T xa[PW], xb[PW];
+    // Panel elimination in registers, one row per lane: lanes 0..15 hold the
+    // panel's diagonal block (rows p..p+15) in every wave, lanes 16..63 of
+    // wave w hold rows p + 16 + 48 w + (lane - 16).  Each wave repeats the
+    // diagonal block's elimination (bitwise the same in all waves) so that
+    // no column has to cross waves; the per-column chain is one broadcast, a
+    // square root, one reciprocal and a Markstein quotient.  Entries above
+    // the diagonal start at zero and are never read back or stored.
+    const int lrow = lane < PW ? p + lane : p + PW + 48 * wave + (lane - PW);
+    if (wave == 0 || p + PW + 48 * wave < mp) {
+      T x[PW];
 #pragma unroll
-      for (int c = 0; c < PW; c++) {
-        xa[c] = (ra >= p && ra < mp) ? a[ra * LD + p + c] : (T)0;
-        xb[c] = (rb >= p && rb < mp) ? a[rb * LD + p + c] : (T)0;
-      }
+      for (int c = 0; c < PW; c++)
+        x[c] = (lrow < mp && lrow >= p + c) ? a[lrow * LD + p + c] : (T)0;
+      int bad = 0;   // 1 + first local column with a pivot <= 0 / NaN / inf
 #pragma unroll
       for (int jj = 0; jj < PW; jj++) {
         const int j = p + jj;
-        const T d = lane_bcast(lo ? xa[jj] : xb[jj], j & 63);
-        if (lane == 0 && j < m && (!(d > (T)0) || !isfinite((double)d)))
-          atomicMin(&st->failed, (unsigned long long)(i0 + j + 1));
+        const T d = lane_bcast(x[jj], jj);
+        if (bad == 0 && j < m && !(d > (T)0 && isfinite((double)d))) bad = j + 1;
         const T ljj = sqrt(d);
-        const T qa = xa[jj] / ljj, qb = xb[jj] / ljj;
-        xa[jj] = ra == j ? ljj : (ra > j ? qa : xa[jj]);
-        xb[jj] = rb == j ? ljj : (rb > j ? qb : xb[jj]);
-        const T colv = lo ? xa[jj] : xb[jj];
+        const T y = (T)1 / ljj;
+        const T q = qdiv(x[jj], ljj, y);
+        x[jj] = lane == jj ? ljj : q;
 #pragma unroll
         for (int kk = jj + 1; kk < PW; kk++) {
-          const int k = p + kk;
-          const T lkj = lane_bcast(colv, k & 63);
-          const T ta = xa[kk] - xa[jj] * lkj, tb = xb[kk] - xb[jj] * lkj;
-          xa[kk] = ra >= k ? ta : xa[kk];
-          xb[kk] = rb >= k ? tb : xb[kk];
+          const T lkj = lane_bcast(x[jj], kk);
+          x[kk] = x[kk] - x[jj] * lkj;   // two roundings, as in the textbook update
         }
       }
+      if (bad && wave == 0 && lane == 0) atomicMin(&st->failed, (unsigned long long)(i0 + bad));
+      if (lrow < mp && (lane >= PW || wave == 0)) {
 #pragma unroll
-      for (int c = 0; c < PW; c++) {
-        if (ra >= p + c && ra < mp) a[ra * LD + p + c] = xa[c];
-        if (rb >= p + c && rb < mp) a[rb * LD + p + c] = xb[c];
+        for (int c = 0; c < PW; c++)
+          if (lrow >= p + c) a[lrow * LD + p + c] = x[c];
       }
     }
     __syncthreads();
