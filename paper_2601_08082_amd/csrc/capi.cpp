@@ -53,6 +53,8 @@ struct mpchol_ctx_s {
   size_t tsv_flag_count = 0;
   double* tsv_x = nullptr;    // published solution blocks (n x kMaxRhs)
   size_t tsv_x_count = 0;
+  double* tsv_yd = nullptr;   // inverses of the 64 x 64 diagonal blocks of L
+  size_t tsv_yd_count = 0;
   unsigned int tsv_epoch = 0;
   double* npart = nullptr;    // norm partials (device)
   double* hnpart = nullptr;   // norm partials (pinned host)
@@ -598,6 +600,7 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->tsv_p) (void)hipFree(c->tsv_p);
   if (c->tsv_flag) (void)hipFree(c->tsv_flag);
   if (c->tsv_x) (void)hipFree(c->tsv_x);
+  if (c->tsv_yd) (void)hipFree(c->tsv_yd);
   if (c->npart) (void)hipFree(c->npart);
   if (c->hnpart) (void)hipHostFree(c->hnpart);
   if (c->dst) (void)hipFree(c->dst);
@@ -677,6 +680,15 @@ static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
     HIPCHK(hipMalloc((void**)&c->tsv_p, sizeof(double) * pc));
     c->tsv_p_count = pc;
   }
+  const size_t yc = (size_t)((n + 63) / 64) * 4096;
+  if (yc > c->tsv_yd_count) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->tsv_yd) HIPCHK(hipFree(c->tsv_yd));
+    c->tsv_yd = nullptr;
+    c->tsv_yd_count = 0;
+    HIPCHK(hipMalloc((void**)&c->tsv_yd, sizeof(double) * yc));
+    c->tsv_yd_count = yc;
+  }
   const size_t xc = (size_t)n * kMaxRhs;
   if (xc > c->tsv_x_count) {
     HIPCHK(hipDeviceSynchronize());
@@ -701,7 +713,8 @@ static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
   return 0;
 }
 
-// X <- L^-T L^-1 X for up to kMaxRhs columns at a time.
+// X <- L^-T L^-1 X for up to kMaxRhs columns at a time (c->tsv_yd holds the
+// diagonal-block inverses of L).
 static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
   const double lbytes = (double)n * (n + 1) / 2 * 8.0;
@@ -713,12 +726,12 @@ static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const doubl
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     HIPCHK(launch_ticket_reset(c->dst, s));
     int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv2(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, items, nitems, c->tsv_p,
+    HIPCHK(launch_trsv2(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd, items, nitems, c->tsv_p,
                         c->tsv_flag,
                         ++c->tsv_epoch, c->dst, 0, s));
     prof_end(c, pk, s);
     pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv2(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, items, nitems, c->tsv_p,
+    HIPCHK(launch_trsv2(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd, items, nitems, c->tsv_p,
                         c->tsv_flag,
                         ++c->tsv_epoch, c->dst, 2, s));
     prof_end(c, pk, s);
@@ -747,6 +760,18 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
   HIPCHK(hipEventRecord(c->ev0, s));
   HIPCHK(launch_status_init(c->dst, s));
   HIPCHK(launch_copy_cols(n, (int)nrhs, B, ldb, X, ldx, s));
+  {
+    int2* items = nullptr;
+    int nitems = 0;
+    int r0 = ensure_trsv(c, n, &items, &nitems);
+    if (r0) return r0;
+    // used by every triangular solve of this call
+    const int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRINV,
+                                             (double)((n + 63) / 64) * 64.0 * 64.0 * 64.0 / 3.0, s)
+                                : -1;
+    HIPCHK(launch_diag_inv(L, ldl, n, c->tsv_yd, s));
+    prof_end(c, pk, s);
+  }
   int r = chol_solve_inplace(c, n, nrhs, L, ldl, X, ldx, s);
   if (r) return r;
   int status = MPCHOL_OK;

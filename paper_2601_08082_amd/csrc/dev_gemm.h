@@ -121,8 +121,9 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
 
   const int m0 = tm * BM, n0 = tn * BN;
-  const Q* __restrict__ X = ws + P.x;
-  const Q* __restrict__ Y = ws + P.y;
+  // an operand whose block scale is not 1 reads its own scaled copy
+  const Q* __restrict__ X = ws + (isx == 1.0 ? P.x : P.x_alt);
+  const Q* __restrict__ Y = ws + (isy == 1.0 ? P.y : P.y_alt);
   const int kv = (P.k + 15) & ~15;  // zero-padded K extent of the copies
   const int nk = (kv + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

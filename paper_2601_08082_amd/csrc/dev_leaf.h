@@ -291,6 +291,9 @@ __device__ inline void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// YD: extent of the written output, Y(0:YD, 0:YD) (m <= YD <= KL); entries
+// outside the lower m x m triangle are written as zeros.
+template <int YD = KL>
 __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, int64_t i0, int m,
                                   double* __restrict__ Y, int ldy, char* lds) {
   double* l = reinterpret_cast<double*>(lds);   // L blocks
@@ -367,9 +370,9 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
   }
   __syncthreads();
 #pragma unroll 8
-  for (int r = 0; r < KL * KL / 256; r++) {
+  for (int r = 0; r < YD * YD / 256; r++) {
     const int idx = tid + 256 * r;
-    const int i = idx % KL, j = idx / KL;   // Y(i, j), column-major, ld ldy
+    const int i = idx % YD, j = idx / YD;   // Y(i, j), column-major, ld ldy
     double v = 0.0;
     if (i < m && j < m && i >= j) v = y[iblk(i >> 4, j >> 4) + (i & 15) * IBP + (j & 15)];
     Y[i + (int64_t)j * ldy] = v;

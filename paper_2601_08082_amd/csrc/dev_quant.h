@@ -137,7 +137,7 @@ __device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, con
   cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);  // 1/s exact
 }
 
-// Scale-1 cast that also records the tile's max |x| in part[jb.part0 + t]: the
+// Scale-1 cast that also records the tile's max |x| in the job's partials: the
 // first half of the single-pass quantization (scale_mode 0: a block whose
 // max |x| fits the format has scale 1).
 template <typename Q>
@@ -147,7 +147,9 @@ __device__ inline void cast_max_tile(const double* __restrict__ Lm, int64_t ldl,
   double* red = reinterpret_cast<double*>(lds);
   __syncthreads();
   const double m = cast_core<Q>(Lm, ldl, jb, t, 1.0, prec, ws, red, lds + 256 * 8, true);
-  if (threadIdx.x == 0) part[jb.part0 + t] = m;
+  // tile row-major, so that the tiles of a row range are contiguous
+  const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
+  if (threadIdx.x == 0) part[jb.part0 + tr * jb.tiles_c + tc] = m;
 }
 
 // Second half, one workgroup per job: the block max |x| from the tile partials

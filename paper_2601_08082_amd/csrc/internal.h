@@ -63,6 +63,9 @@ struct GemmProb {
   int32_t tiles_m, tiles_n;
   int32_t tile_start;  // prefix sum of tiles over the problem list
   int32_t pad;
+  // F16/E4M3: copies to read instead of x / y when that operand's block scale
+  // is not 1 (equal to x / y unless a scale-1 copy is shared between problems)
+  int64_t x_alt, y_alt;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -99,6 +102,9 @@ hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64
                            const double* Y, int ldy, hipStream_t s);
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,
                             int64_t c0, int k, hipStream_t s);
+// Inverses of the 64 x 64 diagonal blocks of L (n x n), block J at
+// Yd + 4096 J (column-major, ld 64, zero outside the lower nj x nj triangle).
+hipError_t launch_diag_inv(const double* Lm, int64_t ldl, int64_t n, double* Yd, hipStream_t s);
 
 // Solve / refinement kernels.
 // R = B - A X (A symmetric, lower stored, read once); work holds
@@ -107,12 +113,14 @@ size_t residual_work_bytes(int64_t n, int nrhs);
 // Load-distributed block solve: ticketed diagonal and helper items (the list
 // from trsv2_items), helper partial sums in P (trsv2_partial_doubles(n)) with
 // epoch-tagged flags (trsv2_flags(n) words, zero before first use), and XP
-// (n x nrhs doubles, ld n) for the published solution blocks.
+// (n x nrhs doubles, ld n) for the published solution blocks.  Yd holds the
+// inverses of the 64 x 64 diagonal blocks (launch_diag_inv).
 int trsv2_items(int64_t n, std::vector<int2>& items);
 size_t trsv2_partial_doubles(int64_t n);
 size_t trsv2_flags(int64_t n);
 hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
-                        int64_t ldx, double* XP, const int2* items, int nitems, double* P,
+                        int64_t ldx, double* XP, const double* Yd, const int2* items, int nitems,
+                        double* P,
                         unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
                         hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,

@@ -61,6 +61,22 @@ __global__ __launch_bounds__(64) void k_small_gemm(double* __restrict__ C, int l
   small_gemm_tile(C, ldc, A, lda, B, ldb, M, N, K, alpha);
 }
 
+// Inverses of the 64 x 64 diagonal blocks of L (the last one ragged), one
+// workgroup each, into Yd (block J at Yd + 4096 J, column-major, ld 64).
+__global__ __launch_bounds__(256) void k_diag_inv(const double* __restrict__ Lm, int64_t ldl,
+                                                  int64_t n, double* __restrict__ Yd) {
+  __shared__ __attribute__((aligned(16))) char pool[trinv_lds_bytes()];
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int nj = (int)min((int64_t)64, n - j0);
+  trinv_body<64>(Lm, ldl, j0, nj, Yd + (int64_t)blockIdx.x * 4096, 64, pool);
+}
+
+hipError_t launch_diag_inv(const double* Lm, int64_t ldl, int64_t n, double* Yd, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, Lm, ldl, n, Yd);
+  return hipGetLastError();
+}
+
 hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y, int ldy,
                         hipStream_t s) {
   if (m <= 0) return hipSuccess;

@@ -80,6 +80,7 @@ template <int NR>
 __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restrict__ Lm,
                                                int64_t ldl, int64_t n, int nrhs, double* X,
                                                int64_t ldx, double* XP,
+                                               const double* __restrict__ Yd,
                                                const int2* __restrict__ items, double* P,
                                                unsigned int* pflag, unsigned int epoch,
                                                DevStatus* st, int slot) {
@@ -100,12 +101,12 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
   const int nj = (int)min((int64_t)NB, n - j0);
   const bool diag = chunk < 0;
   if (diag) {
+    // the inverse of the diagonal block (lower, zero-padded to 64 x 64)
+    const double* Y = Yd + (int64_t)J * NB * NB;
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; u++) {
       const int idx = tid + 256 * u;
-      const int i = idx & 63, q = idx >> 6;
-      const double v = Lm[(j0 + min(i, nj - 1)) + (j0 + min(q, nj - 1)) * ldl];
-      dg[q][i] = (i < nj && q < nj && i >= q) ? v : 0.0;
+      dg[idx >> 6][idx & 63] = Y[idx];   // dg[q][i] = Y(i, q)
     }
   }
   double part[NR];
@@ -205,45 +206,42 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
     }
     return;
   }
+  // v = b - (the folded sums); x = Y v (forward) or Y^T v (transposed)
   if (tid < 64) {
-    const int i = tid;
-    double v[NR];
 #pragma unroll
     for (int c = 0; c < NR; c++) {
-      const double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * ldx] : 0.0;
-      v[c] = b - ((acc[0][i][c] + acc[1][i][c]) + (acc[2][i][c] + acc[3][i][c]));
+      const double bv = (c < nrhs && r < nj) ? X[(j0 + r) + (int64_t)c * ldx] : 0.0;
+      xs[r][c] = bv - ((acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]));
     }
-    const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;
-    if (!trans) {
-      for (int j = 0; j < nj; j++) {
-        const double lij = dg[j][i];
-        const double ij = bcast(inv, j);
+  }
+  __syncthreads();
 #pragma unroll
-        for (int c = 0; c < NR; c++) {
-          const double xj = bcast(v[c], j) * ij;
-          const double upd = v[c] - lij * xj;
-          v[c] = i == j ? xj : (i > j ? upd : v[c]);
-        }
-      }
-    } else {
-      for (int j = nj - 1; j >= 0; j--) {
-        const double lji = dg[i][j];
-        const double ij = bcast(inv, j);
+  for (int c = 0; c < NR; c++) part[c] = 0.0;
+  if (!trans) {
+    for (int q = g; q < NB; q += 4) {
+      const double y = dg[q][r];
 #pragma unroll
-        for (int c = 0; c < NR; c++) {
-          const double xj = bcast(v[c], j) * ij;
-          const double upd = v[c] - lji * xj;
-          v[c] = i == j ? xj : (i < j ? upd : v[c]);
-        }
-      }
+      for (int c = 0; c < NR; c++) part[c] += y * xs[q][c];
     }
+  } else {
+    for (int q = g; q < NB; q += 4) {
+      const double y = dg[r][q];
+#pragma unroll
+      for (int c = 0; c < NR; c++) part[c] += y * xs[q][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
+  __syncthreads();
+  if (tid < 64) {
 #pragma unroll
     for (int c = 0; c < NR; c++)
-      if (c < nrhs && i < nj) {
-        X[(j0 + i) + (int64_t)c * ldx] = v[c];
+      if (c < nrhs && r < nj) {
+        const double v = (acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]);
+        X[(j0 + r) + (int64_t)c * ldx] = v;
         // the published copy, coherent across the dies without a fence
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + i) + (int64_t)c * n),
-                           (unsigned long long)__double_as_longlong(v[c]), __ATOMIC_RELAXED,
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + r) + (int64_t)c * n),
+                           (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
   }
@@ -278,7 +276,7 @@ size_t trsv2_flags(int64_t n) {
 }
 
 hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
-                        int64_t ldx, double* XP, const int2* items, int nitems, double* P,
+                        int64_t ldx, double* XP, const double* Yd, const int2* items, int nitems, double* P,
                         unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
                         hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
@@ -291,19 +289,19 @@ hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int
   }
   dim3 g(nitems), b(256);
   if (nrhs == 1)
-    hipLaunchKernelGGL(k_trsv2<1>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+    hipLaunchKernelGGL(k_trsv2<1>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd, items, P, pflag,
                        epoch, st, ticket_slot);
   else if (nrhs <= 2)
-    hipLaunchKernelGGL(k_trsv2<2>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+    hipLaunchKernelGGL(k_trsv2<2>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd, items, P, pflag,
                        epoch, st, ticket_slot);
   else if (nrhs <= 4)
-    hipLaunchKernelGGL(k_trsv2<4>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+    hipLaunchKernelGGL(k_trsv2<4>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd, items, P, pflag,
                        epoch, st, ticket_slot);
   else if (nrhs <= 8)
-    hipLaunchKernelGGL(k_trsv2<8>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+    hipLaunchKernelGGL(k_trsv2<8>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd, items, P, pflag,
                        epoch, st, ticket_slot);
   else
-    hipLaunchKernelGGL(k_trsv2<16>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, items, P, pflag,
+    hipLaunchKernelGGL(k_trsv2<16>, g, b, 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd, items, P, pflag,
                        epoch, st, ticket_slot);
   return hipGetLastError();
 }

@@ -161,7 +161,133 @@ struct Builder {
     // FP16 with scale_mode 0: one pass casts at scale 1 and records the max-abs
     const bool single_pass = quant && prec == F16 && t.scale_mode == 0 && !single_wg;
     if (single_pass) with_parts = false;
-    for (const Node& nd : nodes) {
+    // Single pass: operands of the group with the same columns whose rows
+    // overlap or touch share one scale-1 copy of the union of their rows (a
+    // SYRK's sub-products read every row of its operand once per recursion
+    // level).  Each operand keeps its own block scale: a fix-up job reduces
+    // the copy's 64 x 64 tile maxima over the operand's rows and, when the
+    // scale is not 1, casts the operand again into a copy of its own that
+    // the GEMM then reads.  Sharing needs operand rows on 64-row tile
+    // boundaries of the union, so the tiles reduced are exactly the
+    // operand's; an operand that is not aligned gets a copy of its own.
+    std::vector<CastJob> views;
+    std::vector<int64_t> view_base_dst;   // the operand's rows in the shared copy
+    std::vector<int> node_x(nodes.size(), -1), node_y(nodes.size(), -1);
+    if (single_pass) {
+      struct Opd { int64_t r, c; int rows, k; };
+      std::vector<Opd> ops;
+      for (size_t i = 0; i < nodes.size(); i++) {
+        const Node& nd = nodes[i];
+        node_x[i] = (int)ops.size();
+        ops.push_back({nd.xr, nd.xc, nd.m, nd.k});
+        if (nd.lower) {
+          node_y[i] = node_x[i];
+        } else {
+          node_y[i] = (int)ops.size();
+          ops.push_back({nd.yr, nd.yc, nd.n, nd.k});
+        }
+      }
+      std::vector<int> opd_view(ops.size(), -1);
+      std::vector<int64_t> base_row;   // first row of each shared copy (index = cast job)
+      std::map<std::pair<int64_t, int>, std::vector<int>> cls;
+      for (int i = 0; i < (int)ops.size(); i++) cls[{ops[i].c, ops[i].k}].push_back(i);
+      auto make_base = [&](int64_t r, int64_t c, int rows, int k) {
+        int ldq = 0;
+        add_cast(cj, prec, r, c, rows, k, {0, 0}, &ldq);
+        CastJob& j = cj.back();
+        j.part0 = (int)part_cursor;   // tile maxima, tile row-major
+        j.nparts = j.tiles_r * j.tiles_c;
+        part_cursor += j.nparts;
+        base_row.resize(cj.size(), 0);
+        base_row.back() = r;
+        return (int)cj.size() - 1;
+      };
+      auto make_view = [&](int oi, int bi, bool own) {
+        const Opd& o = ops[oi];
+        const CastJob& b = cj[bi];
+        const int64_t dr = o.r - base_row[bi];
+        CastJob v{};
+        v.src = off(o.r, o.c);
+        v.rows = o.rows;
+        v.cols = o.k;
+        v.ldq = b.ldq;
+        v.tiles_r = (int)cdiv(o.rows, 64);
+        v.tiles_c = b.tiles_c;
+        v.part0 = b.part0 + (int)(dr / 64) * b.tiles_c;
+        v.nparts = (int)(cdiv(dr + o.rows, 64) - dr / 64) * b.tiles_c;
+        v.final_part = (int)part_cursor++;
+        const int64_t shared_dst = b.dst + dr * b.ldq;
+        if (own) {
+          v.dst = b.dst;   // sole user: cast again in place
+        } else {
+          const int esz = prec == F16 ? 2 : 1;
+          ws_cursor = (size_t)rup((int64_t)ws_cursor, 256);
+          v.dst = (int64_t)(ws_cursor / esz);
+          ws_cursor += (size_t)o.rows * v.ldq * esz;
+        }
+        opd_view[oi] = (int)views.size();
+        views.push_back(v);
+        view_base_dst.push_back(shared_dst);
+      };
+      for (auto& kv : cls) {
+        std::vector<int>& idx = kv.second;
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+          return ops[a].r != ops[b].r ? ops[a].r < ops[b].r : ops[a].rows > ops[b].rows;
+        });
+        size_t i = 0;
+        while (i < idx.size()) {
+          // union of rows overlapping or touching
+          int64_t u0 = ops[idx[i]].r, u1 = u0 + ops[idx[i]].rows;
+          size_t j = i + 1;
+          while (j < idx.size() && ops[idx[j]].r <= u1) {
+            u1 = std::max(u1, ops[idx[j]].r + ops[idx[j]].rows);
+            j++;
+          }
+          std::vector<int> aligned, other;
+          for (size_t q = i; q < j; q++) {
+            const Opd& o = ops[idx[q]];
+            const int64_t a0 = o.r - u0, a1 = o.r + o.rows - u0;
+            if (a0 % 64 == 0 && (a1 % 64 == 0 || o.r + o.rows == u1)) aligned.push_back(idx[q]);
+            else other.push_back(idx[q]);
+          }
+          if (aligned.size() == 1 && ops[aligned[0]].r == u0 && ops[aligned[0]].rows == u1 - u0) {
+            other.push_back(aligned[0]);
+            aligned.clear();
+          }
+          if (!aligned.empty()) {
+            // the shared copy spans the aligned operands' rows only
+            int64_t s0 = INT64_MAX, s1 = INT64_MIN;
+            for (int oi : aligned) {
+              s0 = std::min(s0, ops[oi].r);
+              s1 = std::max(s1, ops[oi].r + ops[oi].rows);
+            }
+            bool ok = true;
+            for (int oi : aligned) {
+              const int64_t a0 = ops[oi].r - s0, a1 = ops[oi].r + ops[oi].rows - s0;
+              if (a0 % 64 != 0 || (a1 % 64 != 0 && ops[oi].r + ops[oi].rows != s1)) ok = false;
+            }
+            if (ok) {
+              const int bi = make_base(s0, kv.first.first, (int)(s1 - s0), kv.first.second);
+              for (int oi : aligned) make_view(oi, bi, false);
+            } else {
+              other.insert(other.end(), aligned.begin(), aligned.end());
+            }
+          }
+          for (int oi : other) {
+            if (opd_view[oi] >= 0) continue;
+            const int bi = make_base(ops[oi].r, ops[oi].c, ops[oi].rows, ops[oi].k);
+            make_view(oi, bi, true);
+          }
+          i = j;
+        }
+      }
+      for (size_t i = 0; i < nodes.size(); i++) {
+        node_x[i] = opd_view[node_x[i]];
+        node_y[i] = opd_view[node_y[i]];
+      }
+    }
+    for (size_t ni = 0; ni < nodes.size(); ni++) {
+      const Node& nd = nodes[ni];
       GemmProb g{};
       g.c = off(nd.cr, nd.cc);
       g.m = nd.m;
@@ -177,42 +303,37 @@ struct Builder {
       g.xnparts = px.second;
       g.ypart0 = py.first;
       g.ynparts = py.second;
-      if (quant) {
+      if (single_pass) {
+        const CastJob& vx = views[node_x[ni]];
+        const CastJob& vy = views[node_y[ni]];
+        g.x = view_base_dst[node_x[ni]];
+        g.x_alt = vx.dst;
+        g.ldx = vx.ldq;
+        g.xpart0 = vx.final_part;
+        g.xnparts = 1;
+        g.y = view_base_dst[node_y[ni]];
+        g.y_alt = vy.dst;
+        g.ldy = vy.ldq;
+        g.ypart0 = vy.final_part;
+        g.ynparts = 1;
+      } else if (quant) {
         int ldx = 0, ldy = 0;
-        // single pass: the tile partials of a job, then its final max-abs slot
-        auto own_parts = [&](CastJob& j) {
-          j.part0 = (int)part_cursor;
-          j.nparts = j.tiles_r * j.tiles_c;
-          j.final_part = j.part0 + j.nparts;
-          part_cursor += j.nparts + 1;
-          return std::make_pair(j.final_part, 1);
-        };
         g.x = add_cast(cj, prec, nd.xr, nd.xc, nd.m, nd.k, px, &ldx);
         g.ldx = ldx;
-        if (single_pass) {
-          px = own_parts(cj.back());
-          g.xpart0 = px.first;
-          g.xnparts = px.second;
-        }
         if (nd.lower) {
           g.y = g.x;
           g.ldy = ldx;
-          if (single_pass) {
-            g.ypart0 = px.first;
-            g.ynparts = px.second;
-          }
         } else {
           g.y = add_cast(cj, prec, nd.yr, nd.yc, nd.n, nd.k, py, &ldy);
           g.ldy = ldy;
-          if (single_pass) {
-            py = own_parts(cj.back());
-            g.ypart0 = py.first;
-            g.ynparts = py.second;
-          }
         }
+        g.x_alt = g.x;
+        g.y_alt = g.y;
       } else {
         g.x = off(nd.xr, nd.xc);
         g.y = off(nd.yr, nd.yc);
+        g.x_alt = g.x;
+        g.y_alt = g.y;
         g.ldx = g.ldy = (int)ldl;
       }
       double fl = nd.lower ? (double)nd.m * (nd.m + 1) * nd.k : 2.0 * nd.m * nd.n * nd.k;
@@ -247,9 +368,10 @@ struct Builder {
       P.launches.push_back(L);
       if (single_pass) {
         Launch F{Launch::CASTFIX, prec};
-        F.first = L.first;
-        F.count = L.count;
-        F.total = L.count;
+        F.first = (int)P.casts.size();
+        F.count = (int)views.size();
+        F.total = F.count;
+        P.casts.insert(P.casts.end(), views.begin(), views.end());
         P.launches.push_back(F);
       }
     }
