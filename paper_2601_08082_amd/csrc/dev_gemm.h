@@ -129,30 +129,33 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  uint4 rx[NV], ry[NV];
-  auto gload = [&](int k0) {
+  // Unconditional loads (K clamped into the copy), the K padding masked when
+  // the values go to LDS: a load under a condition is waited for where it is
+  // issued.  Two register sets are in flight (steps kt + 1 and kt + 2 while
+  // step kt multiplies out of LDS), double-buffered LDS.
+  uint4 rx[2][NV], ry[2][NV];
+  auto gload = [&](int k0, uint4 (&vx)[NV], uint4 (&vy)[NV]) {
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
       int row = v >> 3, ch = v & 7;
-      int kk = k0 + ch * EPV;
       int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
-      if (kk < kv) {
-        rx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kk);
-        ry[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kk);
-      } else {
-        rx[i] = make_uint4(0, 0, 0, 0);
-        ry[i] = make_uint4(0, 0, 0, 0);
-      }
+      const int kc = min(k0 + ch * EPV, kv - EPV);
+      vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+      vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int k0, const uint4 (&vx)[NV], const uint4 (&vy)[NV]) {
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
       int row = v >> 3, ch = v & 7;
-      *reinterpret_cast<uint4*>(&Xs[buf][row * LDSW + ch * EPV]) = rx[i];
-      *reinterpret_cast<uint4*>(&Ys[buf][row * LDSW + ch * EPV]) = ry[i];
+      const unsigned int msk = k0 + ch * EPV < kv ? ~0u : 0u;
+      const uint4 a = vx[i], b = vy[i];
+      *reinterpret_cast<uint4*>(&Xs[buf][row * LDSW + ch * EPV]) =
+          make_uint4(a.x & msk, a.y & msk, a.z & msk, a.w & msk);
+      *reinterpret_cast<uint4*>(&Ys[buf][row * LDSW + ch * EPV]) =
+          make_uint4(b.x & msk, b.y & msk, b.z & msk, b.w & msk);
     }
   };
 
@@ -164,12 +167,7 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[a][b][r] = 0.0f;
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; kt++) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK / 16; kk++) {
       const int koff = kk * 16 + 8 * (lane >> 5);
@@ -185,25 +183,58 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
 #pragma unroll
         for (int b = 0; b < NF; b++) acc[a][b] = QOps<Q>::mfma(af[a], bf[b], acc[a][b]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+  auto step = [&](int kt, uint4 (&nx)[NV], uint4 (&ny)[NV], uint4 (&sx)[NV], uint4 (&sy)[NV]) {
+    gload((kt + 2) * BK, nx, ny);
+    // keep the loads ahead of the products (the scheduler would otherwise
+    // sink them to their use and wait for them on the spot)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(kt & 1);
+    // unconditional (past the end it fills a buffer nobody reads): a store
+    // under a condition pulls the loads it consumes into its branch
+    sstore((kt + 1) & 1, (kt + 1) * BK, sx, sy);
     __syncthreads();
-  }
+  };
 
+  gload(0, rx[0], ry[0]);
+  gload(BK, rx[1], ry[1]);
+  sstore(0, 0, rx[0], ry[0]);
+  __syncthreads();
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    step(kt, rx[0], ry[0], rx[1], ry[1]);
+    step(kt + 1, rx[1], ry[1], rx[0], ry[0]);
+  }
+  if (kt < nk) step(kt, rx[0], ry[0], rx[1], ry[1]);
+
+  // C tile, one 32-column strip of the wave tile at a time: every load of
+  // the strip first (addresses clamped into the block), then the stores; a
+  // read-modify-write per element under its condition would wait for each
+  // load in turn
   double* __restrict__ C = Lm + P.c;
 #pragma unroll
-  for (int a = 0; a < NF; a++)
+  for (int a = 0; a < NF; a++) {
+    double cv[NF][16];
+#pragma unroll
+    for (int b = 0; b < NF; b++) {
+      const int m = min(m0 + wm * WT + b * 32 + (lane & 31), P.m - 1);
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int n = min(n0 + wn * WT + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), P.n - 1);
+        cv[b][r] = C[m + (int64_t)n * ldl];
+      }
+    }
 #pragma unroll
     for (int b = 0; b < NF; b++) {
       const int m = m0 + wm * WT + b * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int n = n0 + wn * WT + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m < P.m && n < P.n && (!P.lower || m >= n)) {
-          double* p = C + m + (int64_t)n * ldl;
-          *p = *p - sxy * (double)acc[a][b][r];
-        }
+        if (m < P.m && n < P.n && (!P.lower || m >= n))
+          C[m + (int64_t)n * ldl] = cv[b][r] - sxy * (double)acc[a][b][r];
       }
     }
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -227,18 +258,25 @@ template <> struct DOps<double> {
   }
 };
 
+// K step of the FP32 / FP64 tiles: FP32 takes 32 (the operands arrive as
+// FP64, so a step moves 2 x BM x 32 x 8 bytes), FP64 16 (LDS).
+template <typename T> constexpr int gemm_d_bk() { return sizeof(T) == 4 ? 32 : 16; }
+
 template <typename T, int BM>
 constexpr int gemm_d_lds_bytes() {
-  return 2 * 2 * 16 * ((int)sizeof(T) == 8 ? BM + 16 : BM + 32) * (int)sizeof(T) + 256 * 8;
+  return 2 * 2 * gemm_d_bk<T>() * ((int)sizeof(T) == 8 ? BM + 16 : BM + 32) * (int)sizeof(T) +
+         256 * 8;
 }
 
 // One output tile t of problem P, FP32/FP64 operands read from the factor.
+// Two register sets of loads are in flight (steps kt + 1 and kt + 2 while
+// step kt multiplies out of LDS), double-buffered LDS.
 template <typename T, int BM>
 __device__ inline void gemm_d_tile(double* __restrict__ Lm, int64_t ldl, const GemmProb& P,
                                    int t, const double* __restrict__ part, int prec,
                                    int scale_mode, DevStatus* st, char* lds) {
   typedef typename DOps<T>::acc_t acc_t;
-  constexpr int BN = BM, BK = 16;                // square tiles: 128 or 64
+  constexpr int BN = BM, BK = gemm_d_bk<T>();    // square tiles: 128 or 64
   constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
   constexpr int NF = WT / 16;                    // 16 x 16 MFMA tiles per wave dimension
   constexpr int NL = BM * BK / 256;              // elements per thread per operand and K step
@@ -262,32 +300,37 @@ __device__ inline void gemm_d_tile(double* __restrict__ Lm, int64_t ldl, const G
   const int nk = (P.k + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  const int mm = tid % BM;
+  const bool xin = m0 + mm < P.m, yin = n0 + mm < P.n;
+  const double* __restrict__ Xr = X + min(m0 + mm, P.m - 1);
+  const double* __restrict__ Yr = Y + min(n0 + mm, P.n - 1);
 
-  T rx[NL], ry[NL];
-  auto gload = [&](int k0) {
-    const int mm = tid % BM;
+  // Loads are unconditional (addresses clamped into the block; a step past
+  // the end loads in-bounds values nobody uses) and the padding is zeroed
+  // when the values go to LDS: a select on a loaded value, or a load under a
+  // condition, makes the compiler wait for the load where it is issued.
+  double rx[2][NL], ry[2][NL];
+  auto gload = [&](int k0, double (&vx)[NL], double (&vy)[NL]) {
 #pragma unroll
     for (int i = 0; i < NL; i++) {
-      int kk = k0 + (tid / BM) + TPR * i;
-      bool kin = kk < P.k;
-      double vx = (kin && m0 + mm < P.m) ? X[(m0 + mm) + (int64_t)kk * ldl] : 0.0;
-      double vy = (kin && n0 + mm < P.n) ? Y[(n0 + mm) + (int64_t)kk * ldl] : 0.0;
-      if constexpr (sizeof(T) == 4) {
-        rx[i] = (float)(vx * isx);
-        ry[i] = (float)(vy * isy);
-      } else {
-        rx[i] = vx;
-        ry[i] = vy;
-      }
+      const int kc = min(k0 + (tid / BM) + TPR * i, P.k - 1);
+      vx[i] = Xr[(int64_t)kc * ldl];
+      vy[i] = Yr[(int64_t)kc * ldl];
     }
   };
-  auto sstore = [&](int buf) {
-    const int mm = tid % BM;
+  auto sstore = [&](int buf, int k0, const double (&vx)[NL], const double (&vy)[NL]) {
 #pragma unroll
     for (int i = 0; i < NL; i++) {
-      int kk = (tid / BM) + TPR * i;
-      Xs[buf][kk * LDSW + mm] = rx[i];
-      Ys[buf][kk * LDSW + mm] = ry[i];
+      const int kk = (tid / BM) + TPR * i;
+      const bool kin = k0 + kk < P.k;
+      const double a = (kin && xin) ? vx[i] : 0.0, b = (kin && yin) ? vy[i] : 0.0;
+      if constexpr (sizeof(T) == 4) {
+        Xs[buf][kk * LDSW + mm] = (float)(a * isx);
+        Ys[buf][kk * LDSW + mm] = (float)(b * isy);
+      } else {
+        Xs[buf][kk * LDSW + mm] = a;
+        Ys[buf][kk * LDSW + mm] = b;
+      }
     }
   };
 
@@ -299,12 +342,7 @@ __device__ inline void gemm_d_tile(double* __restrict__ Lm, int64_t ldl, const G
 #pragma unroll
       for (int r = 0; r < 4; r++) acc[a][b][r] = 0;
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; kt++) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; kk++) {
       const int krow = kk * 4 + (lane >> 4);
@@ -318,11 +356,51 @@ __device__ inline void gemm_d_tile(double* __restrict__ Lm, int64_t ldl, const G
 #pragma unroll
         for (int b = 0; b < NF; b++) acc[a][b] = DOps<T>::mfma(af[a], bf[b], acc[a][b]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+  // step kt: loads of step kt + 2 into the set freed at step kt - 1, multiply
+  // LDS buffer kt & 1, then LDS buffer (kt + 1) & 1 from the other set
+  auto step = [&](int kt, double (&nx)[NL], double (&ny)[NL], double (&sx)[NL],
+                  double (&sy)[NL]) {
+    gload((kt + 2) * BK, nx, ny);
+    // keep the loads ahead of the products (the scheduler would otherwise
+    // sink them to their use and wait for them on the spot)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(kt & 1);
+    // unconditional (past the end it fills a buffer nobody reads): a store
+    // under a condition pulls the loads it consumes into its branch
+    sstore((kt + 1) & 1, (kt + 1) * BK, sx, sy);
     __syncthreads();
-  }
+  };
 
+  gload(0, rx[0], ry[0]);
+  gload(BK, rx[1], ry[1]);
+  sstore(0, 0, rx[0], ry[0]);
+  __syncthreads();
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    step(kt, rx[0], ry[0], rx[1], ry[1]);
+    step(kt + 1, rx[1], ry[1], rx[0], ry[0]);
+  }
+  if (kt < nk) step(kt, rx[0], ry[0], rx[1], ry[1]);
+
+  // C tile: every load first (addresses clamped into the block), then the
+  // stores; a read-modify-write per element under its condition would wait
+  // for each load in turn
   double* __restrict__ C = Lm + P.c;
+  double cv[NF][NF][4];
+#pragma unroll
+  for (int a = 0; a < NF; a++)
+#pragma unroll
+    for (int b = 0; b < NF; b++) {
+      const int m = min(m0 + wm * WT + b * 16 + (lane & 15), P.m - 1);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int n = min(n0 + wn * WT + a * 16 +
+                              (sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r),
+                          P.n - 1);
+        cv[a][b][r] = C[m + (int64_t)n * ldl];
+      }
+    }
 #pragma unroll
   for (int a = 0; a < NF; a++)
 #pragma unroll
@@ -332,10 +410,8 @@ __device__ inline void gemm_d_tile(double* __restrict__ Lm, int64_t ldl, const G
       for (int r = 0; r < 4; r++) {
         const int n = n0 + wn * WT + a * 16 +
                       (sizeof(T) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
-        if (m < P.m && n < P.n && (!P.lower || m >= n)) {
-          double* p = C + m + (int64_t)n * ldl;
-          *p = *p - sxy * (double)acc[a][b][r];
-        }
+        if (m < P.m && n < P.n && (!P.lower || m >= n))
+          C[m + (int64_t)n * ldl] = cv[a][b][r] - sxy * (double)acc[a][b][r];
       }
     }
 }

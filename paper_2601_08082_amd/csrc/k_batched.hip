@@ -24,6 +24,7 @@ constexpr int kProfClasses = 11;                       // per-class timing slots
 static_assert(kPool >= potrf_leaf_lds_bytes<double>(), "pool");
 static_assert(kPool >= gemm_q_lds_bytes<_Float16, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<double, 128>(), "pool");
+static_assert(kPool >= gemm_d_lds_bytes<float, 128>(), "pool");
 
 __device__ inline int find_job_max(const MaxabsJob* j, int nj, int w) {
   int lo = 0, hi = nj - 1;
