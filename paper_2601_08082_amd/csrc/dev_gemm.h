@@ -22,7 +22,10 @@ __device__ inline int find_prob(const GemmProb* __restrict__ probs, int nprobs, 
 }
 
 // Tile (tm, tn) of problem P for local tile index t.  Lower problems enumerate
-// only tiles with tm >= tn (column by column).
+// only tiles with tm >= tn (column by column).  Full problems go through
+// bands of 8 tile rows, each band column by column, so that consecutive
+// tiles (which run at the same time on one XCD, see xcd_tile) share 8 row
+// panels and a few column panels in that XCD's L2.
 __device__ inline void tile_coords(const GemmProb& P, int t, int* tm, int* tn) {
   if (P.lower) {
     int c = 0, rem = t, T = P.tiles_m;
@@ -30,9 +33,22 @@ __device__ inline void tile_coords(const GemmProb& P, int t, int* tm, int* tn) {
     *tn = c;
     *tm = c + rem;
   } else {
-    *tm = t % P.tiles_m;
-    *tn = t / P.tiles_m;
+    constexpr int GM = 8;
+    const int per_band = GM * P.tiles_n;
+    const int band = t / per_band, r = t - band * per_band;
+    const int m0 = band * GM, gm = min(P.tiles_m - m0, GM);
+    *tm = m0 + r % gm;
+    *tn = r / gm;
   }
+}
+
+// Logical tile of workgroup w of a grid of `total`: workgroups are dealt to
+// the 8 XCDs round-robin (w % 8), so XCD x gets a contiguous range of
+// logical tiles instead of every 8th one.
+__device__ inline int xcd_tile(int w, int total) {
+  const int per = total >> 3, rem = total & 7;
+  const int x = w & 7, j = w >> 3;
+  return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
 __device__ inline double reduce_max(const double* __restrict__ part, int p0, int np,
@@ -90,9 +106,12 @@ template <> struct QOps<unsigned char> {
   }
 };
 
+// Bytes of each operand row per K step.
+template <int BM> constexpr int gemm_q_kbytes() { return 128; }
+
 template <typename Q, int BM>
 constexpr int gemm_q_lds_bytes() {
-  return 2 * 2 * BM * (128 / (int)sizeof(Q) + 16 / (int)sizeof(Q)) * (int)sizeof(Q) + 256 * 8;
+  return 2 * 2 * BM * (gemm_q_kbytes<BM>() + 16) + 256 * 8;
 }
 
 // One output tile t of problem P (workgroup-level; lds = gemm_q_lds_bytes()).
@@ -105,10 +124,11 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   constexpr int BN = BM;                         // square tiles: 128 or 64
   constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
   constexpr int NF = WT / 32;                    // 32 x 32 MFMA tiles per wave dimension
-  constexpr int NV = BM * 8 / 256;               // 16-byte vectors per thread per operand
+  constexpr int CPR = gemm_q_kbytes<BM>() / 16;  // 16-byte chunks per row and K step
+  constexpr int NV = BM * CPR / 256;             // 16-byte vectors per thread per operand
   constexpr int EPV = 16 / (int)sizeof(Q);       // elements per 16-byte vector
-  constexpr int BK = 128 / (int)sizeof(Q);       // elements per K step (128 bytes per row)
-  constexpr int LDSW = BK + EPV;                 // padded LDS row (144 bytes)
+  constexpr int BK = CPR * EPV;                  // elements per K step
+  constexpr int LDSW = BK + EPV;                 // padded LDS row (one chunk)
   typedef Q QTile[BM * LDSW];
   QTile* Xs = reinterpret_cast<QTile*>(lds);
   QTile* Ys = Xs + 2;
@@ -138,7 +158,7 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
-      int row = v >> 3, ch = v & 7;
+      int row = v / CPR, ch = v % CPR;
       int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
       const int kc = min(k0 + ch * EPV, kv - EPV);
       vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
@@ -149,7 +169,7 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
-      int row = v >> 3, ch = v & 7;
+      int row = v / CPR, ch = v % CPR;
       const unsigned int msk = k0 + ch * EPV < kv ? ~0u : 0u;
       const uint4 a = vx[i], b = vy[i];
       *reinterpret_cast<uint4*>(&Xs[buf][row * LDSW + ch * EPV]) =

@@ -22,8 +22,9 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
                                                 const double* __restrict__ part, int prec,
                                                 int scale_mode, DevStatus* st) {
   __shared__ __attribute__((aligned(16))) char pool[gemm_q_lds_bytes<Q, BM>()];
-  const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
-  gemm_q_tile<Q, BM>(Lm, ldl, ws, P, blockIdx.x - P.tile_start, part, prec, scale_mode, st, pool);
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb P = probs[find_prob(probs, nprobs, w)];
+  gemm_q_tile<Q, BM>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
 }
 
 template <typename T, int BM>
@@ -32,8 +33,9 @@ __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t
                                                 const double* __restrict__ part, int prec,
                                                 int scale_mode, DevStatus* st) {
   __shared__ __attribute__((aligned(16))) char pool[gemm_d_lds_bytes<T, BM>()];
-  const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
-  gemm_d_tile<T, BM>(Lm, ldl, P, blockIdx.x - P.tile_start, part, prec, scale_mode, st, pool);
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb P = probs[find_prob(probs, nprobs, w)];
+  gemm_d_tile<T, BM>(Lm, ldl, P, w - P.tile_start, part, prec, scale_mode, st, pool);
 }
 
 template <int BM>

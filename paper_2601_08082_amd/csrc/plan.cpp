@@ -395,8 +395,7 @@ struct Builder {
         L.tile = mn >= 128 ? 128 : 64;
       } else {
         // 128 x 128 tiles unless that leaves most of the 256 CUs idle (256 x
-        // 256 tiles of this kernel measured slower at every level-0 shape:
-        // one workgroup per CU cannot hide the load latency)
+        // 256 tiles measured slower: one wave per SIMD, fewer loads in flight)
         L.tile = tiles_of(128) >= 256 ? 128 : 64;
       }
       int tiles = 0;
