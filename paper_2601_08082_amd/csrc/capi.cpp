@@ -177,6 +177,7 @@ static double launch_work(const Plan& P, const Launch& L) {
     w = 2.0 * (double)(L.a1 - L.a2) * L.a2 * L.a1;   // the two products
   } else if (L.kind == Launch::POTRF || L.kind == Launch::TRINV) {
     w = (double)L.a1 * L.a1 * L.a1 / 3.0;
+    if (L.kind == Launch::POTRF && L.a2 == 1) w *= 2.0;   // with the inverse
   } else {
     w = (double)L.a1 * L.a3 * L.a3;
   }
@@ -244,7 +245,11 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
     const int pk = c->prof_mask ? prof_begin(c, launch_kind(Lc), launch_work(P, Lc), s) : -1;
     switch (Lc.kind) {
       case Launch::POTRF:
-        e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, s);
+        if (Lc.a2 == 1)
+          e = launch_potrf_inv(L, ldl, Lc.a0, (int)Lc.a1, c->dst,
+                               c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
+        else
+          e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, s);
         break;
       case Launch::TRSM:
         if (Lc.first >= 0)
@@ -948,7 +953,8 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
           if (L.kind == Launch::TRINV || L.kind == Launch::CASTFIX || L.kind == Launch::INVJOIN ||
-              (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0)) {
+              (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0) ||
+              (L.kind == Launch::POTRF && L.a2 == 1)) {
             free_batch(c);
             return MPCHOL_HIP_ERROR;   // workgroup-level plans never use leaf inverses
           }

@@ -64,8 +64,8 @@ template <typename T>
 constexpr int potrf_leaf_lds_bytes() { return KL * (KL + 1) * (int)sizeof(T); }
 
 template <typename T>
-__device__ inline void potrf_leaf_body(double* __restrict__ Lm, int64_t ldl, int64_t i0, int m,
-                                       DevStatus* st, char* lds) {
+__device__ __attribute__((always_inline)) inline void potrf_leaf_body(
+    double* __restrict__ Lm, int64_t ldl, int64_t i0, int m, DevStatus* st, char* lds) {
   constexpr int LD = KL + 1;
   T* a = reinterpret_cast<T*>(lds);   // a[i * LD + j], row-major, lower part used
   __syncthreads();   // the pool may still be in use by the previous task
@@ -292,8 +292,10 @@ __device__ inline void wave_lds_order() {
 }
 
 // YD: extent of the written output, Y(0:YD, 0:YD) (m <= YD <= KL); entries
-// outside the lower m x m triangle are written as zeros.
-template <int YD = KL>
+// outside the lower m x m triangle are written as zeros.  FROM_LDS: L is
+// taken from the leaf POTRF's LDS copy at the start of the pool (row-major,
+// row stride KL + 1) instead of from Lm, and the pool is then reused.
+template <int YD = KL, bool FROM_LDS = false>
 __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, int64_t i0, int m,
                                   double* __restrict__ Y, int ldy, char* lds) {
   double* l = reinterpret_cast<double*>(lds);   // L blocks
@@ -308,8 +310,12 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
     for (int r = 0; r < KL * KL / 256; r++) {
       const int idx = tid + 256 * r;
       const int i = idx % KL, j = idx / KL;
-      v[r] = A[min(i, m - 1) + (int64_t)min(j, m - 1) * ldl];
+      if constexpr (FROM_LDS)
+        v[r] = reinterpret_cast<const double*>(lds)[min(i, m - 1) * (KL + 1) + min(j, m - 1)];
+      else
+        v[r] = A[min(i, m - 1) + (int64_t)min(j, m - 1) * ldl];
     }
+    if constexpr (FROM_LDS) __syncthreads();   // every copy read before the pool is rewritten
 #pragma unroll
     for (int r = 0; r < KL * KL / 256; r++) {
       const int idx = tid + 256 * r;

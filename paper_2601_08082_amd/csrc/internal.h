@@ -96,6 +96,10 @@ hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int 
 // order k <= 2 KL.
 hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double* Y, int ldy,
                         hipStream_t s);
+// Leaf POTRF of A(i0:i0+m, i0:i0+m) (FP64, m <= 128) and the inverse of the
+// new factor into Y (ld ldy >= 128; the 128 x 128 region is written).
+hipError_t launch_potrf_inv(double* Lm, int64_t ldl, int64_t i0, int m, DevStatus* st, double* Y,
+                           int ldy, hipStream_t s);
 hipError_t launch_inv_join(const double* Lm, int64_t ldl, int64_t i0, int m, int m1, double* Y,
                            int ldy, double* T, hipStream_t s);
 hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,

@@ -17,9 +17,10 @@
 // overflow/underflow, with three dependent operations instead of a full
 // division on the elimination chain.
 //
-// FP64 leaves can instead be solved through their inverse: k_trinv forms
-// Y = L^{-1} once per leaf (block substitution, FP64 MFMA for the
-// off-diagonal blocks) and k_trsm_inv computes B <- B Y^T as an FP64 MFMA
+// FP64 leaves can instead be solved through their inverse: k_potrf_inv (or
+// k_trinv on its own) forms Y = L^{-1} once per leaf (block substitution,
+// FP64 MFMA for the off-diagonal blocks; k_potrf_inv right after the
+// factorization, from its LDS copy) and k_trsm_inv computes B <- B Y^T as an FP64 MFMA
 // product, 16 rows per workgroup, with no dependency chain along the
 // columns.  Same values up to rounding; the substitution kernel remains the
 // bit-exact reference mode.
@@ -39,6 +40,19 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(double* __restrict__ Lm, int6
                                                    int64_t r0, int64_t m, int64_t c0, int k) {
   __shared__ __attribute__((aligned(16))) char pool[trsm_leaf_lds_bytes<T>()];
   trsm_leaf_rows<T>(Lm, ldl, r0, m, c0, k, blockIdx.x, pool);
+}
+
+// FP64 leaf POTRF followed, in the same workgroup, by the inverse of the new
+// factor, taken from the factor's LDS copy.
+__global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ Lm, int64_t ldl,
+                                                   int64_t i0, int m, DevStatus* st,
+                                                   double* __restrict__ Y, int ldy) {
+  constexpr int kBytes = potrf_leaf_lds_bytes<double>() > trinv_lds_bytes()
+                             ? potrf_leaf_lds_bytes<double>()
+                             : trinv_lds_bytes();
+  __shared__ __attribute__((aligned(16))) char pool[kBytes];
+  potrf_leaf_body<double>(Lm, ldl, i0, m, st, pool);
+  trinv_body<KL, true>(Lm, ldl, i0, m, Y, ldy, pool);
 }
 
 __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Lm, int64_t ldl,
@@ -74,6 +88,14 @@ __global__ __launch_bounds__(256) void k_diag_inv(const double* __restrict__ Lm,
 hipError_t launch_diag_inv(const double* Lm, int64_t ldl, int64_t n, double* Yd, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, Lm, ldl, n, Yd);
+  return hipGetLastError();
+}
+
+hipError_t launch_potrf_inv(double* Lm, int64_t ldl, int64_t i0, int m, DevStatus* st, double* Y,
+                           int ldy, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (m > KL || ldy < KL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_potrf_inv, dim3(1), dim3(256), 0, s, Lm, ldl, i0, m, st, Y, ldy);
   return hipGetLastError();
 }
 

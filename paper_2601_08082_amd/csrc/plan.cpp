@@ -428,17 +428,15 @@ struct Builder {
       Launch L{Launch::POTRF, t.leaf_prec};
       L.a0 = i0;
       L.a1 = m;
+      if (use_inverse()) {
+        // the inverse is formed by the same launch (a2 = 1) into slot `first`
+        L.a2 = 1;
+        L.first = slot >= 0 ? slot : P.ninv++;
+        L.off = slot >= 0 ? off : 0;
+        inv_slot[{i0, m}] = {L.first, L.off};
+      }
       P.launches.push_back(L);
       P.stats.leaf_flops += (double)m * m * m / 3.0;
-      if (use_inverse()) {
-        Launch I{Launch::TRINV, F64};
-        I.a0 = i0;
-        I.a1 = m;
-        I.first = slot >= 0 ? slot : P.ninv++;
-        I.off = slot >= 0 ? off : 0;
-        inv_slot[{i0, m}] = {I.first, I.off};
-        P.launches.push_back(I);
-      }
       return;
     }
     int64_t m1 = leaf_split(m), m2 = m - m1;

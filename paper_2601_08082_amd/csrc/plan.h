@@ -14,11 +14,13 @@ namespace mpc {
 struct Launch {
   enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, CASTFIX, INVJOIN } kind;
   int prec;
-  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m; TRSM: r0, m, c0, k;
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m (POTRF a2 = 1: also
+                                          // the inverse); TRSM: r0, m, c0, k;
                                           // CAST: a0 = 1 single-pass (scale 1 + max-abs)
-  int first = 0, count = 0, total = 0;    // descriptor range, workgroups; TRINV / TRSM /
-                                          // INVJOIN: leaf-inverse slot (TRSM: -1 = substitution)
-  int64_t off = 0;                        // TRINV / TRSM: element offset in the slot
+  int first = 0, count = 0, total = 0;    // descriptor range, workgroups; POTRF / TRINV /
+                                          // TRSM / INVJOIN: leaf-inverse slot (TRSM: -1 =
+                                          // substitution)
+  int64_t off = 0;                        // POTRF / TRINV / TRSM: element offset in the slot
                                           // (INVJOIN: a0 = i0, a1 = m, a2 = m1)
   int tile = 128;                         // GEMM output tile (64 or 128)
 };
