@@ -55,12 +55,15 @@ constexpr int CW = 8;
 // arithmetic produces)
 constexpr unsigned long long kSentinel = 0x7FF4D5A1B2C3E4F5ull;
 
-__device__ inline bool wait_flag(unsigned int* f, unsigned int epoch, DevStatus* st) {
+// Wait until every flag f[0 .. count) holds `epoch` (thread t polls flags
+// t, t + 256, ...), then one agent-scope acquire.  False after a timeout.
+__device__ inline bool wait_flags(unsigned int* f, int count, unsigned int epoch, DevStatus* st) {
   __shared__ int ok;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
     long spins = 0;
-    ok = 1;
-    while (atomic_load_rlx(f) != epoch) {
+    while (atomic_load_rlx(&f[i]) != epoch) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) {
         atomicOr(&st->wait_timeout, 1u);
@@ -68,12 +71,32 @@ __device__ inline bool wait_flag(unsigned int* f, unsigned int epoch, DevStatus*
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  bool r = ok != 0;
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
-  return r;
+  return ok != 0;
+}
+
+// v, or +0 when `keep` is false, without a select on the loaded value (the
+// compiler turns such a select into a branch that waits for the load)
+__device__ inline double keep_or_zero(double v, bool keep) {
+  return __longlong_as_double(__double_as_longlong(v) & (keep ? -1ll : 0ll));
+}
+
+// x_K(i, c) from its published copy: every value is written once per call
+// over a sentinel, so a value that is not the sentinel is final.
+__device__ inline double poll_x(const double* XP, int64_t at, DevStatus* st) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(const_cast<double*>(XP) + at);
+  unsigned long long b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  long spins = 0;
+  while (b == kSentinel && spins < kSpinLimit) {
+    __builtin_amdgcn_s_sleep(1);
+    ++spins;
+    b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (b == kSentinel) atomicOr(&st->wait_timeout, 1u);
+  return b == kSentinel ? 0.0 : __longlong_as_double((long long)b);
 }
 
 template <int NR>
@@ -84,9 +107,10 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
                                                const int2* __restrict__ items, double* P,
                                                unsigned int* pflag, unsigned int epoch,
                                                DevStatus* st, int slot) {
-  __shared__ double blk[NB][NB + 1];
-  __shared__ double dg[NB][NB + 1];
-  __shared__ double xs[NB][NR];
+  constexpr int NL = NB * NB / 256;   // block elements per thread
+  __shared__ double blk[NB][NB + 1];  // transposed solves: the block, transposed through LDS
+  __shared__ double dg[NB][NB + 1];   // diagonal items: the block's inverse
+  __shared__ double xs[2][NB][NR];
   __shared__ double acc[4][NB][NR];
   __shared__ unsigned int my_ticket;
   const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
@@ -100,28 +124,47 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
   const int64_t j0 = (int64_t)J * NB;
   const int nj = (int)min((int64_t)NB, n - j0);
   const bool diag = chunk < 0;
+  double bval[NR];
   if (diag) {
-    // the inverse of the diagonal block (lower, zero-padded to 64 x 64)
+    // the inverse of the diagonal block (lower, zero-padded to 64 x 64) and
+    // the right-hand side, loaded up front (both are off the chain)
     const double* Y = Yd + (int64_t)J * NB * NB;
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; u++) {
+    for (int u = 0; u < NL; u++) {
       const int idx = tid + 256 * u;
       dg[idx >> 6][idx & 63] = Y[idx];   // dg[q][i] = Y(i, q)
     }
+#pragma unroll
+    for (int c = 0; c < NR; c++)
+      bval[c] = keep_or_zero(X[(j0 + min(r, nj - 1)) + (int64_t)min(c, nrhs - 1) * ldx],
+                             tid < 64 && c < nrhs && r < nj);
   }
   double part[NR];
 #pragma unroll
   for (int c = 0; c < NR; c++) part[c] = 0.0;
   int k_begin, k_end;
   if (diag) {
-    // helper sums of the chunks before the window, in chunk order
+    // helper sums of the chunks before the window, added in chunk order
     const int hc = sidx / CW - 1;      // chunks 0 .. hc - 1
-    for (int c2 = 0; c2 < hc; c2++) {
-      if (!wait_flag(&pflag[(int64_t)sidx * nch + c2], epoch, st)) return;
+    if (hc > 0) {
+      if (!wait_flags(&pflag[(int64_t)sidx * nch], hc, epoch, st)) return;
       if (g == 0) {
-        const double* pp = P + ((int64_t)sidx * nch + c2) * NB * NR;
+        // 16 loads in flight at a time
+        constexpr int G = NR >= 16 ? 1 : 16 / NR;
+        for (int c0 = 0; c0 < hc; c0 += G) {
+          double v[G][NR];
 #pragma unroll
-        for (int c = 0; c < NR; c++) part[c] += coherent_load(&pp[r * NR + c]);
+          for (int j = 0; j < G; j++) {
+            const double* pp = P + ((int64_t)sidx * nch + min(c0 + j, hc - 1)) * NB * NR;
+#pragma unroll
+            for (int c = 0; c < NR; c++)
+              v[j][c] = keep_or_zero(coherent_load(&pp[r * NR + c]), c0 + j < hc);
+          }
+#pragma unroll
+          for (int j = 0; j < G; j++)
+#pragma unroll
+            for (int c = 0; c < NR; c++) part[c] += v[j][c];
+        }
       }
     }
     k_begin = max(0, CW * (sidx / CW) - CW);
@@ -130,63 +173,67 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
     k_begin = chunk * CW;
     k_end = chunk * CW + CW;
   }
-  for (int sk = k_begin; sk < k_end; sk++) {
+  // Blocks K = k_begin .. k_end - 1: the next block's loads are in flight
+  // while this one waits for x_K.  Thread (r, g) holds L(j0 + r, k0 + g + 4u)
+  // (forward) or L(k0 + r, j0 + g + 4u) (transposed, regrouped through LDS).
+  auto load_blk = [&](int sk, double (&v)[NL]) {
     const int K = trans ? nblk - 1 - sk : sk;
     const int64_t k0 = (int64_t)K * NB;
     const int nk = (int)min((int64_t)NB, n - k0);
-    double tmp[NB * NB / 256];
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; u++) {
-      const int idx = tid + 256 * u;
-      const int i = idx & 63, q = idx >> 6;
-      double v;
-      if (!trans)
-        v = Lm[(j0 + min(i, nj - 1)) + (k0 + min(q, nk - 1)) * ldl];
-      else
-        v = Lm[(k0 + min(i, nk - 1)) + (j0 + min(q, nj - 1)) * ldl];
-      const bool in = trans ? (i < nk && q < nj) : (i < nj && q < nk);
-      tmp[u] = in ? v : 0.0;
+    for (int u = 0; u < NL; u++) {
+      const int q = g + 4 * u;
+      const int64_t row = trans ? k0 + min(r, nk - 1) : j0 + min(r, nj - 1);
+      const int64_t col = trans ? j0 + min(q, nj - 1) : k0 + min(q, nk - 1);
+      v[u] = Lm[row + col * ldl];
     }
-    __syncthreads();
+  };
+  auto step = [&](int sk, double (&cur)[NL], double (&nxt)[NL]) {
+    load_blk(min(sk + 1, k_end - 1), nxt);   // past the end: a block nobody uses
+    const int K = trans ? nblk - 1 - sk : sk;
+    const int64_t k0 = (int64_t)K * NB;
+    const int nk = (int)min((int64_t)NB, n - k0);
+    const int buf = sk & 1;
+    if (trans) {
+      __syncthreads();   // the previous block's readers are done with blk
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; u++) {
-      const int idx = tid + 256 * u;
-      blk[idx >> 6][idx & 63] = tmp[u];
+      for (int u = 0; u < NL; u++) {
+        const int q = g + 4 * u;
+        blk[q][r] = keep_or_zero(cur[u], r < nk && q < nj);   // blk[q][i] = L(k0 + i, j0 + q)
+      }
     }
-    // x_K from its published copy: every value is written once per call over
-    // a sentinel, so a value that is not the sentinel is final
     for (int idx = tid; idx < NB * NR; idx += 256) {
       const int i = idx % NB, c = idx / NB;
-      double v = 0.0;
-      if (i < nk && c < nrhs) {
-        unsigned long long* p =
-            reinterpret_cast<unsigned long long*>(XP + (k0 + i) + (int64_t)c * n);
-        unsigned long long b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        long spins = 0;
-        while (b == kSentinel && spins < kSpinLimit) {
-          __builtin_amdgcn_s_sleep(1);
-          ++spins;
-          b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (b == kSentinel) atomicOr(&st->wait_timeout, 1u);
-        v = b == kSentinel ? 0.0 : __longlong_as_double((long long)b);
-      }
-      xs[i][c] = v;
+      xs[buf][i][c] = (i < nk && c < nrhs) ? poll_x(XP, (k0 + i) + (int64_t)c * n, st) : 0.0;
     }
     __syncthreads();
     if (!trans) {
-      for (int q = g; q < NB; q += 4) {
-        const double l = blk[q][r];
 #pragma unroll
-        for (int c = 0; c < NR; c++) part[c] += l * xs[q][c];
+      for (int u = 0; u < NL; u++) {
+        const int q = g + 4 * u;
+        const double l = keep_or_zero(cur[u], r < nj && q < nk);
+#pragma unroll
+        for (int c = 0; c < NR; c++) part[c] += l * xs[buf][q][c];
       }
     } else {
-      for (int i = g; i < NB; i += 4) {
+#pragma unroll
+      for (int u = 0; u < NL; u++) {
+        const int i = g + 4 * u;
         const double l = blk[r][i];
 #pragma unroll
-        for (int c = 0; c < NR; c++) part[c] += l * xs[i][c];
+        for (int c = 0; c < NR; c++) part[c] += l * xs[buf][i][c];
       }
     }
+  };
+  if (k_begin < k_end) {
+    double la[NL], lb[NL];
+    load_blk(k_begin, la);
+    int sk = k_begin;
+    for (; sk + 1 < k_end; sk += 2) {
+      step(sk, la, lb);
+      step(sk + 1, lb, la);
+    }
+    if (sk < k_end) step(sk, la, lb);
   }
   __syncthreads();
 #pragma unroll
@@ -209,10 +256,8 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
   // v = b - (the folded sums); x = Y v (forward) or Y^T v (transposed)
   if (tid < 64) {
 #pragma unroll
-    for (int c = 0; c < NR; c++) {
-      const double bv = (c < nrhs && r < nj) ? X[(j0 + r) + (int64_t)c * ldx] : 0.0;
-      xs[r][c] = bv - ((acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]));
-    }
+    for (int c = 0; c < NR; c++)
+      xs[0][r][c] = bval[c] - ((acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]));
   }
   __syncthreads();
 #pragma unroll
@@ -221,15 +266,16 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
     for (int q = g; q < NB; q += 4) {
       const double y = dg[q][r];
 #pragma unroll
-      for (int c = 0; c < NR; c++) part[c] += y * xs[q][c];
+      for (int c = 0; c < NR; c++) part[c] += y * xs[0][q][c];
     }
   } else {
     for (int q = g; q < NB; q += 4) {
       const double y = dg[r][q];
 #pragma unroll
-      for (int c = 0; c < NR; c++) part[c] += y * xs[q][c];
+      for (int c = 0; c < NR; c++) part[c] += y * xs[0][q][c];
     }
   }
+  __syncthreads();   // every wave has read acc
 #pragma unroll
   for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
   __syncthreads();
