@@ -193,8 +193,11 @@ def evaluate(ctx, params, n: int = 32768, ratio: float = 1.1, leaf: int = 256, r
     choice = ctx.policy_choose(A, n, tree, params)
     torch.cuda.synchronize()
     choose_ms = (time.perf_counter() - t0) * 1e3
+    # fixed_f16_scaled scales blocks the way the learned tree does (scale_mode
+    # 1, also up); fixed_f16 uses scale_mode 0, whose FP16 casts are one pass
     trees = {
         "learned": M.Tree(leaf=leaf, offdiag=[M.F16], scale_mode=1, node_prec=choice),
+        "fixed_f16_scaled": M.Tree(leaf=leaf, offdiag=[M.F16], scale_mode=1),
         "fixed_f16": M.Tree(leaf=leaf, offdiag=[M.F16]),
         "fp64": M.Tree(leaf=leaf, offdiag=[M.F64]),
     }
@@ -227,6 +230,8 @@ def evaluate(ctx, params, n: int = 32768, ratio: float = 1.1, leaf: int = 256, r
     out["choice_matches_labels"] = float(np.mean(np.array(lab) == np.array(choice)))
     out["speedup_learned_vs_fp64"] = out["fp64"]["tts_ms"] / out["learned"]["tts_ms"]
     out["speedup_learned_vs_fixed"] = out["fixed_f16"]["tts_ms"] / out["learned"]["tts_ms"]
+    out["speedup_learned_vs_fixed_scaled"] = (out["fixed_f16_scaled"]["tts_ms"] /
+                                              out["learned"]["tts_ms"])
     return out
 
 
