@@ -93,9 +93,11 @@ def test_integer_factor_bitwise(M, ctx, n, ti):
     assert np.max(np.abs(np.tril(L[:n, :n]) - L0)) <= 1e-13 * np.max(np.abs(L0))
 
 
-@pytest.mark.parametrize("n,leaf", [(5, 4), (100, 37), (300, 64), (700, 128), (1111, 200)])
+@pytest.mark.parametrize("n,leaf", [(5, 4), (100, 37), (300, 64), (700, 128), (1111, 200),
+                                    (2600, 256), (3001, 128)])
 def test_leaf_inverse_trsm_vs_substitution(M, ctx, n, leaf):
-    """The two leaf-TRSM modes agree to FP64 rounding on ragged leaves."""
+    """The two leaf-TRSM modes agree to FP64 rounding on ragged leaves; the
+    last two sizes also solve strips of more than 1024 rows."""
     import dataclasses
     print(f"[gpu] leaf inverse vs substitution n={n} leaf={leaf}", flush=True)
     A = spdgen.gen_spd(n, 1.1, 0.0, seed=n + 5)
