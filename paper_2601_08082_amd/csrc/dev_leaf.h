@@ -330,6 +330,11 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
   if (tid < nb * IB) {
     const int bb = tid >> 4, c = tid & 15;
     const double* L = l + iblk(bb, bb);
+    // the 16 reciprocals of the pivots are independent: all divisions first,
+    // then the substitution multiplies
+    double dinv[IB];
+#pragma unroll
+    for (int r = 0; r < IB; r++) dinv[r] = 1.0 / L[r * IBP + r];
     double x[IB];
 #pragma unroll
     for (int r = 0; r < IB; r++) {
@@ -337,7 +342,7 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
 #pragma unroll
       for (int k = 0; k < r; k++)
         if (k >= c) s = s - L[r * IBP + k] * x[k];
-      x[r] = r < c ? 0.0 : s / L[r * IBP + r];
+      x[r] = r < c ? 0.0 : s * dinv[r];
     }
     double* Yd = y + iblk(bb, bb);
 #pragma unroll

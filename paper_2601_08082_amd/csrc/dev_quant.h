@@ -53,26 +53,34 @@ __device__ inline double reduce_parts(const double* __restrict__ part, int p0, i
 template <typename Q>
 constexpr int cast_lds_bytes() { return 256 * 8 + 64 * (64 + 8) * (int)sizeof(Q); }
 
-// Tile t (64 x 64) of a job's transposing quantize with block scale 1 / inv_s:
-// all loads of a thread in flight, then 16-byte (FP16) / 8-byte (E4M3) row
-// stores of the K-contiguous copy.  With want_max, returns the tile's max |x|
-// (NaN/Inf -> +Inf) to every thread (red: 256 doubles of LDS).
-template <typename Q>
-__device__ inline double cast_core(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
-                                   int t, double inv_s, int prec, Q* __restrict__ ws, double* red,
-                                   char* tile_lds, bool want_max) {
-  typedef Q Row[64 + 8];
-  Row* tile = reinterpret_cast<Row*>(tile_lds);
+// Loads of tile t of a job: v[i] = src(r0 + lane, c0 + wave + 4 i), addresses
+// clamped into the block.
+__device__ inline void cast_load(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
+                                 int t, double (&v)[16]) {
   const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
   const int r0 = tr * 64, c0 = tc * 64;
   const int rr = threadIdx.x & 63;
-  double v[16];
 #pragma unroll
   for (int i = 0; i < 16; i++) {
     const int cc = (threadIdx.x >> 6) + 4 * i;
     const int r = min(r0 + rr, jb.rows - 1), c = min(c0 + cc, jb.cols - 1);
     v[i] = Lm[jb.src + r + (int64_t)c * ldl];
   }
+}
+
+// The rest of the tile from its loaded values: codes through LDS, then
+// 16-byte (FP16) / 8-byte (E4M3) row stores of the K-contiguous copy.  With
+// want_max, returns the tile's max |x| (NaN/Inf -> +Inf) to every thread
+// (red: 256 doubles of LDS).
+template <typename Q>
+__device__ inline double cast_finish(const CastJob& jb, int t, const double (&v)[16], double inv_s,
+                                     int prec, Q* __restrict__ ws, double* red, char* tile_lds,
+                                     bool want_max) {
+  typedef Q Row[64 + 8];
+  Row* tile = reinterpret_cast<Row*>(tile_lds);
+  const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
+  const int r0 = tr * 64, c0 = tc * 64;
+  const int rr = threadIdx.x & 63;
   double m = 0.0;
 #pragma unroll
   for (int i = 0; i < 16; i++) {
@@ -122,6 +130,17 @@ __device__ inline double cast_core(const double* __restrict__ Lm, int64_t ldl, c
   return m;
 }
 
+// Tile t (64 x 64) of a job's transposing quantize with block scale 1 / inv_s:
+// all loads of a thread in flight, then the codes and the row stores.
+template <typename Q>
+__device__ inline double cast_core(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
+                                   int t, double inv_s, int prec, Q* __restrict__ ws, double* red,
+                                   char* tile_lds, bool want_max) {
+  double v[16];
+  cast_load(Lm, ldl, jb, t, v);
+  return cast_finish<Q>(jb, t, v, inv_s, prec, ws, red, tile_lds, want_max);
+}
+
 // Tile t (64 x 64) of the job's transposing quantize, with the block scale
 // from the job's max-abs partials.
 template <typename Q>
@@ -137,19 +156,45 @@ __device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, con
   cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);  // 1/s exact
 }
 
-// Scale-1 cast that also records the tile's max |x| in the job's partials: the
-// first half of the single-pass quantization (scale_mode 0: a block whose
-// max |x| fits the format has scale 1).
+// Scale-1 cast that also records each tile's max |x| in the job's partials:
+// the first half of the single-pass quantization (scale_mode 0: a block whose
+// max |x| fits the format has scale 1), for every w = w0, w0 + stride, ...
+// < total (global tile index over the job list): the loads of the next tile
+// are in flight while this tile is encoded and stored.
 template <typename Q>
-__device__ inline void cast_max_tile(const double* __restrict__ Lm, int64_t ldl, const CastJob& jb,
-                                     int t, double* __restrict__ part, int prec,
-                                     Q* __restrict__ ws, char* lds) {
+__device__ inline void cast_max_tiles(const double* __restrict__ Lm, int64_t ldl,
+                                      const CastJob* __restrict__ jobs, int njobs, int w0,
+                                      int stride, int total, double* __restrict__ part, int prec,
+                                      Q* __restrict__ ws, char* lds) {
   double* red = reinterpret_cast<double*>(lds);
-  __syncthreads();
-  const double m = cast_core<Q>(Lm, ldl, jb, t, 1.0, prec, ws, red, lds + 256 * 8, true);
-  // tile row-major, so that the tiles of a row range are contiguous
-  const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
-  if (threadIdx.x == 0) part[jb.part0 + tr * jb.tiles_c + tc] = m;
+  auto find = [&](int w) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].wg_start <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  if (w0 >= total) return;
+  int j = find(w0);
+  double v[16], vn[16];
+  cast_load(Lm, ldl, jobs[j], w0 - jobs[j].wg_start, v);
+  for (int w = w0; w < total; w += stride) {
+    const int wn = min(w + stride, total - 1);   // past the end: a tile nobody uses
+    const int jn = find(wn);
+    cast_load(Lm, ldl, jobs[jn], wn - jobs[jn].wg_start, vn);
+    __builtin_amdgcn_sched_barrier(0);   // keep those loads here, ahead of this tile's work
+    const CastJob& jb = jobs[j];
+    const int t = w - jb.wg_start;
+    __syncthreads();   // the previous tile's readers of the LDS tile are done
+    const double m = cast_finish<Q>(jb, t, v, 1.0, prec, ws, red, lds + 256 * 8, true);
+    // tile row-major, so that the tiles of a row range are contiguous
+    const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
+    if (threadIdx.x == 0) part[jb.part0 + tr * jb.tiles_c + tc] = m;
+#pragma unroll
+    for (int i = 0; i < 16; i++) v[i] = vn[i];
+    j = jn;
+  }
 }
 
 // Second half, one workgroup per job: the block max |x| from the tile partials

@@ -4,6 +4,8 @@
 // at scale 1 that records the max-abs, and a per-block fix-up that re-casts
 // the rare block whose scale is not 1 - same values either way); plus the
 // small housekeeping kernels of a factorization.
+#include <algorithm>
+
 #include "dev_quant.h"
 
 namespace mpc {
@@ -67,16 +69,10 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ Lm, int
 template <typename Q>
 __global__ __launch_bounds__(256) void k_cast_max(const double* __restrict__ Lm, int64_t ldl,
                                                   const CastJob* __restrict__ jobs, int njobs,
-                                                  double* __restrict__ part, int prec,
+                                                  int total, double* __restrict__ part, int prec,
                                                   Q* __restrict__ ws) {
   __shared__ __attribute__((aligned(16))) char pool[cast_lds_bytes<Q>()];
-  int wg = blockIdx.x;
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].wg_start <= wg) lo = mid; else hi = mid - 1;
-  }
-  cast_max_tile<Q>(Lm, ldl, jobs[lo], wg - jobs[lo].wg_start, part, prec, ws, pool);
+  cast_max_tiles<Q>(Lm, ldl, jobs, njobs, blockIdx.x, gridDim.x, total, part, prec, ws, pool);
 }
 
 template <typename Q>
@@ -91,12 +87,15 @@ __global__ __launch_bounds__(256) void k_cast_fixup(const double* __restrict__ L
 hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                            int total_wg, double* part, int prec, void* ws, hipStream_t s) {
   if (njobs <= 0 || total_wg <= 0) return hipSuccess;
+  // at most 4 workgroups per CU, each looping over tiles with the next one's
+  // loads in flight
+  const unsigned g = (unsigned)std::min(total_wg, 256 * 4);
   if (prec == F16)
-    hipLaunchKernelGGL(k_cast_max<_Float16>, dim3(total_wg), dim3(256), 0, s, Lm, ldl, jobs, njobs,
-                       part, prec, (_Float16*)ws);
+    hipLaunchKernelGGL(k_cast_max<_Float16>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs, njobs,
+                       total_wg, part, prec, (_Float16*)ws);
   else
-    hipLaunchKernelGGL(k_cast_max<unsigned char>, dim3(total_wg), dim3(256), 0, s, Lm, ldl, jobs,
-                       njobs, part, prec, (unsigned char*)ws);
+    hipLaunchKernelGGL(k_cast_max<unsigned char>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs,
+                       njobs, total_wg, part, prec, (unsigned char*)ws);
   return hipGetLastError();
 }
 
