@@ -390,6 +390,9 @@ __global__ __launch_bounds__(256) void k_resid_part(const double* __restrict__ A
 #pragma unroll
   for (int c = 0; c < NR; c++) rowacc[c] = 0.0;
   double tmp[NB * NB / 256];
+  // One unconditional load per element (the address, not the value, is
+  // selected; a select between two loads, or of a loaded value, becomes a
+  // branch that waits for each load in turn); padding is masked on the bits.
   auto fetch = [&](int64_t J) {
     const int64_t j0 = J * NB;
     const int nj = (int)min((int64_t)NB, n - j0);
@@ -399,8 +402,8 @@ __global__ __launch_bounds__(256) void k_resid_part(const double* __restrict__ A
       const int i = min(idx & 63, ni - 1), q = min(idx >> 6, nj - 1);
       // diagonal tile: the upper half is the mirror of the lower (never read)
       const bool mirror = J == I && i < q;
-      const double v = mirror ? A[(i0 + q) + (j0 + i) * lda] : A[(i0 + i) + (j0 + q) * lda];
-      tmp[u] = ((idx & 63) < ni && (idx >> 6) < nj) ? v : 0.0;
+      const int64_t at = mirror ? (i0 + q) + (j0 + i) * lda : (i0 + i) + (j0 + q) * lda;
+      tmp[u] = keep_or_zero(A[at], (idx & 63) < ni && (idx >> 6) < nj);
     }
   };
   fetch(J0);
@@ -415,9 +418,11 @@ __global__ __launch_bounds__(256) void k_resid_part(const double* __restrict__ A
     }
     for (int idx = tid; idx < NB * NR; idx += 256) {
       const int q = idx & 63, c = idx >> 6;
-      xj[q][c] = (q < nj && c < nrhs) ? X[(j0 + q) + (int64_t)c * ldx] : 0.0;
+      xj[q][c] = keep_or_zero(X[(j0 + min(q, nj - 1)) + (int64_t)min(c, nrhs - 1) * ldx],
+                              q < nj && c < nrhs);
     }
-    if (J + 1 < J1) fetch(J + 1);
+    fetch(min(J + 1, J1 - 1));   // past the end: a tile nobody uses
+    __builtin_amdgcn_sched_barrier(0);   // those loads stay ahead of this tile's work
     __syncthreads();
     // rows of I: sum over q = g mod 4 of A_sym(r, q) x_J(q)
     for (int q = g; q < NB; q += 4) {
