@@ -408,9 +408,11 @@ __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64
   int cbs[PER];
 #pragma unroll
   for (int h = 0; h < PER; h++) cbs[h] = (h & 1) ? 4 * (h + 1) - 1 - wave : 4 * h + wave;
-  int lbmax = -1;
-#pragma unroll
-  for (int h = 0; h < PER; h++) lbmax = max(lbmax, cbs[h] < nb ? cbs[h] : -1);
+  // Every load is unconditional from a clamped address and masked on its bits
+  // (a select on a loaded value becomes a branch that waits for the load).
+  auto keep = [](double v, bool ok) {
+    return __longlong_as_double(__double_as_longlong(v) & (ok ? -1ll : 0ll));
+  };
   // A fragments: a[lb][q] = B(lane%16, 16 lb + 4 q + lane/16)
   double a[NCB][4];
   const int ri = min(lane & 15, rows - 1);
@@ -419,27 +421,40 @@ __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       const int col = 16 * lb + 4 * q + (lane >> 4);
-      const double v = B[ri + (int64_t)min(col, k - 1) * ldl];
-      a[lb][q] = (lb <= lbmax && col < k && (lane & 15) < rows) ? v : 0.0;
+      a[lb][q] = keep(B[ri + (int64_t)min(col, k - 1) * ldl], col < k && (lane & 15) < rows);
     }
+  // B-operand fragments of k-chunk lb for this wave's column blocks:
+  // (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk); the next chunk's are in
+  // flight while this chunk's products run
+  auto yload = [&](int lb, double (&f)[PER][4]) {
+#pragma unroll
+    for (int h = 0; h < PER; h++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int yr = 16 * cbs[h] + (lane & 15), yc = 16 * lb + 4 * q + (lane >> 4);
+        f[h][q] = keep(Y[min(yr, k - 1) + (int64_t)min(yc, k - 1) * ldy],
+                       lb <= cbs[h] && yr < k && yc < k);
+      }
+  };
   f64x4 acc[PER];
 #pragma unroll
-  for (int h = 0; h < PER; h++) {
-    acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const int cb = cbs[h];
-    if (cb >= nb) continue;
+  for (int h = 0; h < PER; h++) acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ya[PER][4], yn[PER][4];
+  yload(0, ya);
 #pragma unroll
-    for (int lb = 0; lb < NCB; lb++) {
-      if (lb <= cb) {   // wave-uniform
+  for (int lb = 0; lb < NCB; lb++) {
+    if (lb + 1 < NCB) yload(lb + 1, yn);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-          // B operand (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk)
-          const double bv =
-              Y[(16 * cb + (lane & 15)) + (int64_t)(16 * lb + 4 * q + (lane >> 4)) * ldy];
-          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], bv, acc[h], 0, 0, 0);
-        }
-      }
-    }
+    for (int h = 0; h < PER; h++)
+      if (lb <= cbs[h] && cbs[h] < nb)   // wave-uniform
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], ya[h][q], acc[h], 0, 0, 0);
+#pragma unroll
+    for (int h = 0; h < PER; h++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) ya[h][q] = yn[h][q];
   }
   __syncthreads();   // every wave has consumed its reads of B
 #pragma unroll
