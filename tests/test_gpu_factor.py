@@ -313,10 +313,11 @@ def test_cast_bitwise(M, ctx, prec, mode, shape, scale_pow):
     assert np.all(got[:rows, cols:] == 0)
 
 
-@pytest.mark.parametrize("n,leaf", [(500, 64), (1100, 128)])
+@pytest.mark.parametrize("n,leaf", [(500, 64), (1100, 128), (1024, 64)])
 def test_large_magnitude_block_scales(M, ctx, n, leaf):
     """Entries far above the FP16 range: every quantized block needs a scale
-    above 1 (the single-pass cast re-casts those blocks); the result follows
+    above 1 (the single-pass cast re-casts those blocks; at n = 1024 the
+    operands of a launch also share their scale-1 copies); the result follows
     the oracle's per-block scaling to the mixed-precision bars."""
     print(f"[gpu] large-magnitude scales n={n}", flush=True)
     A = spdgen.gen_spd(n, 1.3, 0.0, seed=n + 21) * 2.0 ** 44   # exact scaling
@@ -327,6 +328,29 @@ def test_large_magnitude_block_scales(M, ctx, n, leaf):
     L64, _, _ = O.factor(A, tree=O.Tree(leaf=leaf, offdiag=[O.F64]))
     assert st == O.OK
     assert np.max(np.abs(np.tril(L64[:n, :n], -1))) > 65504.0   # operands above the FP16 range
+    be_g, be_e = O.backward_error(A, L), O.backward_error(A, Le)
+    assert 0.5 <= be_g / be_e <= 2.0, (be_g, be_e)
+    d_ge = np.linalg.norm(np.tril(L[:n, :n]) - np.tril(Le[:n, :n]))
+    d_e64 = np.linalg.norm(np.tril(Le[:n, :n]) - np.tril(L64[:n, :n]))
+    assert d_ge <= 0.25 * d_e64, (d_ge, d_e64)
+
+
+def test_mixed_magnitude_shared_copies(M, ctx):
+    """A = D A0 D with every other 64-row block of D at 2^30: operands that
+    share one scale-1 copy (n = 1024, leaf 64, aligned splits) have block
+    scales of 1 and above 1 side by side, so some read the shared copy and
+    others their own re-cast copy."""
+    n, leaf = 1024, 64
+    print(f"[gpu] mixed-magnitude shared copies n={n}", flush=True)
+    A0 = spdgen.gen_spd(n, 1.3, 0.0, seed=4242)
+    d = np.where((np.arange(n) // 64) % 2 == 1, 2.0 ** 30, 1.0)
+    A = np.asfortranarray(A0 * d[:, None] * d[None, :])   # exact scaling by powers of two
+    t = M.Tree(leaf=leaf, offdiag=[M.F16, M.F16, M.F32])
+    L, info = _gpu_factor(M, ctx, A, n, t)
+    assert info["status"] == M.OK, info
+    Le, st, _ = O.factor(A, tree=_otree(M, t))
+    L64, _, _ = O.factor(A, tree=O.Tree(leaf=leaf, offdiag=[O.F64]))
+    assert st == O.OK
     be_g, be_e = O.backward_error(A, L), O.backward_error(A, Le)
     assert 0.5 <= be_g / be_e <= 2.0, (be_g, be_e)
     d_ge = np.linalg.norm(np.tril(L[:n, :n]) - np.tril(Le[:n, :n]))
