@@ -161,7 +161,7 @@ static double launch_work(const Plan& P, const Launch& L) {
       w += g.lower ? (double)g.m * (g.m + 1) * g.k : 2.0 * g.m * g.n * g.k;
     }
   } else if (L.kind == Launch::CAST) {
-    int esz = L.prec == F16 ? 2 : 1;
+    int esz = L.prec == F32 ? 4 : L.prec == F16 ? 2 : 1;
     for (int i = 0; i < L.count; i++) {
       const CastJob& j = P.casts[L.first + i];
       w += (double)j.rows * j.cols * (8.0 + esz);

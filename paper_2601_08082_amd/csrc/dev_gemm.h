@@ -258,6 +258,155 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
 }
 
 // ------------------------------------------------------------------------
+// FP32 operands from K-contiguous FP32 workspace copies, v_mfma_f32_16x16x4f32.
+// A lane reads 4 consecutive k (16 bytes) of its row and feeds them to four
+// MFMAs: in MFMA j, lane l supplies k = 16 c + 4 (l / 16) + j of chunk c for
+// both operands, so the four products together cover the chunk's 16 k (the
+// order of k inside a product does not matter).  D(i, j) for lane l,
+// register r: j = l % 16, i = 4 (l / 16) + r.
+
+template <int BM>
+constexpr int gemm_f32q_lds_bytes() { return 2 * 2 * BM * (32 + 4) * 4 + 256 * 8; }
+
+template <int BM>
+__device__ inline void gemm_f32q_tile(double* __restrict__ Lm, int64_t ldl,
+                                      const float* __restrict__ ws, const GemmProb& P, int t,
+                                      const double* __restrict__ part, int prec, int scale_mode,
+                                      DevStatus* st, char* lds) {
+  constexpr int BN = BM;                         // square tiles: 128 or 64
+  constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
+  constexpr int NF = WT / 16;                    // 16 x 16 MFMA tiles per wave dimension
+  constexpr int CPR = 8;                         // 16-byte chunks per row and K step
+  constexpr int NV = BM * CPR / 256;             // 16-byte vectors per thread per operand
+  constexpr int BK = 32;                         // floats per K step
+  constexpr int LDSW = BK + 4;                   // padded LDS row (one chunk)
+  typedef float FTile[BM * LDSW];
+  FTile* Xs = reinterpret_cast<FTile*>(lds);
+  FTile* Ys = Xs + 2;
+  double* red = reinterpret_cast<double*>(Ys + 2);
+  __syncthreads();   // the pool may still be in use by the previous task
+
+  int tm, tn;
+  tile_coords(P, t, &tm, &tn);
+  double isx, isy;
+  const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
+
+  const int m0 = tm * BM, n0 = tn * BN;
+  // an operand whose block scale is not 1 reads its own scaled copy
+  const float* __restrict__ X = ws + (isx == 1.0 ? P.x : P.x_alt);
+  const float* __restrict__ Y = ws + (isy == 1.0 ? P.y : P.y_alt);
+  const int kv = (P.k + 15) & ~15;  // zero-padded K extent of the copies
+  const int nk = (kv + BK - 1) / BK;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  // unconditional loads (K clamped into the copy), padding masked at the LDS
+  // store; two register sets in flight, double-buffered LDS
+  uint4 rx[2][NV], ry[2][NV];
+  auto gload = [&](int k0, uint4 (&vx)[NV], uint4 (&vy)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      int v = tid + 256 * i;
+      int row = v / CPR, ch = v % CPR;
+      int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+      const int kc = min(k0 + ch * 4, kv - 4);
+      vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+      vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+    }
+  };
+  auto sstore = [&](int buf, int k0, const uint4 (&vx)[NV], const uint4 (&vy)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      int v = tid + 256 * i;
+      int row = v / CPR, ch = v % CPR;
+      const unsigned int msk = k0 + ch * 4 < kv ? ~0u : 0u;
+      const uint4 a = vx[i], b = vy[i];
+      *reinterpret_cast<uint4*>(&Xs[buf][row * LDSW + ch * 4]) =
+          make_uint4(a.x & msk, a.y & msk, a.z & msk, a.w & msk);
+      *reinterpret_cast<uint4*>(&Ys[buf][row * LDSW + ch * 4]) =
+          make_uint4(b.x & msk, b.y & msk, b.z & msk, b.w & msk);
+    }
+  };
+
+  f32x4 acc[NF][NF];
+#pragma unroll
+  for (int a = 0; a < NF; a++)
+#pragma unroll
+    for (int b = 0; b < NF; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) acc[a][b][r] = 0.0f;
+
+  auto compute = [&](int cur) {
+#pragma unroll
+    for (int c = 0; c < BK / 16; c++) {
+      const int koff = 16 * c + 4 * (lane >> 4);
+      f32x4 af[NF], bf[NF];
+#pragma unroll
+      for (int a = 0; a < NF; a++)
+        af[a] = *reinterpret_cast<const f32x4*>(&Ys[cur][(wn * WT + a * 16 + (lane & 15)) * LDSW + koff]);
+#pragma unroll
+      for (int b = 0; b < NF; b++)
+        bf[b] = *reinterpret_cast<const f32x4*>(&Xs[cur][(wm * WT + b * 16 + (lane & 15)) * LDSW + koff]);
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+#pragma unroll
+        for (int a = 0; a < NF; a++)
+#pragma unroll
+          for (int b = 0; b < NF; b++)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][j], bf[b][j], acc[a][b], 0, 0, 0);
+    }
+  };
+  auto step = [&](int kt, uint4 (&nx)[NV], uint4 (&ny)[NV], uint4 (&sx)[NV], uint4 (&sy)[NV]) {
+    gload((kt + 2) * BK, nx, ny);
+    // keep the loads ahead of the products (the scheduler would otherwise
+    // sink them to their use and wait for them on the spot)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(kt & 1);
+    // unconditional (past the end it fills a buffer nobody reads)
+    sstore((kt + 1) & 1, (kt + 1) * BK, sx, sy);
+    __syncthreads();
+  };
+
+  gload(0, rx[0], ry[0]);
+  gload(BK, rx[1], ry[1]);
+  sstore(0, 0, rx[0], ry[0]);
+  __syncthreads();
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    step(kt, rx[0], ry[0], rx[1], ry[1]);
+    step(kt + 1, rx[1], ry[1], rx[0], ry[0]);
+  }
+  if (kt < nk) step(kt, rx[0], ry[0], rx[1], ry[1]);
+
+  // C tile, one 16-column strip of the wave tile at a time: every load of
+  // the strip first (addresses clamped into the block), then the stores
+  double* __restrict__ C = Lm + P.c;
+#pragma unroll
+  for (int a = 0; a < NF; a++) {
+    double cv[NF][4];
+#pragma unroll
+    for (int b = 0; b < NF; b++) {
+      const int m = min(m0 + wm * WT + b * 16 + (lane & 15), P.m - 1);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int n = min(n0 + wn * WT + a * 16 + 4 * (lane >> 4) + r, P.n - 1);
+        cv[b][r] = C[m + (int64_t)n * ldl];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NF; b++) {
+      const int m = m0 + wm * WT + b * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int n = n0 + wn * WT + a * 16 + 4 * (lane >> 4) + r;
+        if (m < P.m && n < P.n && (!P.lower || m >= n))
+          C[m + (int64_t)n * ldl] = cv[b][r] - sxy * (double)acc[a][b][r];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
 // FP32 / FP64 operands read straight from the factor (column-major).  FP32
 // operands are rounded (RNE) from FP64 after scaling on the way into LDS.
 // v_mfma_{f32_16x16x4f32, f64_16x16x4f64}: lane l holds A(l%16, k = l/16);

@@ -69,7 +69,8 @@ __device__ inline void cast_load(const double* __restrict__ Lm, int64_t ldl, con
 }
 
 // The rest of the tile from its loaded values: codes through LDS, then
-// 16-byte (FP16) / 8-byte (E4M3) row stores of the K-contiguous copy.  With
+// 32-byte (FP32) / 16-byte (FP16) / 8-byte (E4M3) row stores of the
+// K-contiguous copy.  With
 // want_max, returns the tile's max |x| (NaN/Inf -> +Inf) to every thread
 // (red: 256 doubles of LDS).
 template <typename Q>
@@ -86,20 +87,32 @@ __device__ inline double cast_finish(const CastJob& jb, int t, const double (&v)
   for (int i = 0; i < 16; i++) {
     const int cc = (threadIdx.x >> 6) + 4 * i;
     const bool in = r0 + rr < jb.rows && c0 + cc < jb.cols;
-    uint32_t bits = 0u;
-    if (in) {
-      double a = fabs(v[i]);
-      if (!(a <= 1.7976931348623157e308)) a = __longlong_as_double(0x7FF0000000000000ll);
-      m = fmax(m, a);
-      bits = encode_bits(v[i] * inv_s, prec);
-    }
     Q q;
-    if constexpr (sizeof(Q) == 2) {
-      unsigned short b16 = (unsigned short)bits;
-      q = *reinterpret_cast<Q*>(&b16);
+    if constexpr (sizeof(Q) == 4) {
+      // FP32: the hardware conversion rounds to nearest even (gradual
+      // underflow, overflow to Inf)
+      q = 0.0f;
+      if (in) {
+        double a = fabs(v[i]);
+        if (!(a <= 1.7976931348623157e308)) a = __longlong_as_double(0x7FF0000000000000ll);
+        m = fmax(m, a);
+        q = (float)(v[i] * inv_s);
+      }
     } else {
-      unsigned char b8 = (unsigned char)bits;
-      q = *reinterpret_cast<Q*>(&b8);
+      uint32_t bits = 0u;
+      if (in) {
+        double a = fabs(v[i]);
+        if (!(a <= 1.7976931348623157e308)) a = __longlong_as_double(0x7FF0000000000000ll);
+        m = fmax(m, a);
+        bits = encode_bits(v[i] * inv_s, prec);
+      }
+      if constexpr (sizeof(Q) == 2) {
+        unsigned short b16 = (unsigned short)bits;
+        q = *reinterpret_cast<Q*>(&b16);
+      } else {
+        unsigned char b8 = (unsigned char)bits;
+        q = *reinterpret_cast<Q*>(&b8);
+      }
     }
     tile[rr][cc] = q;
   }
@@ -120,7 +133,10 @@ __device__ inline double cast_finish(const CastJob& jb, int t, const double (&v)
     const int gr = r0 + r, gc = c0 + ch;
     if (gr < jb.rows && gc < jb.ldq) {
       Q* dst = ws + jb.dst + (int64_t)gr * jb.ldq + gc;
-      if constexpr (sizeof(Q) == 2) {
+      if constexpr (sizeof(Q) == 4) {
+        reinterpret_cast<uint4*>(dst)[0] = reinterpret_cast<const uint4*>(&tile[r][ch])[0];
+        reinterpret_cast<uint4*>(dst)[1] = reinterpret_cast<const uint4*>(&tile[r][ch])[1];
+      } else if constexpr (sizeof(Q) == 2) {
         *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&tile[r][ch]);
       } else {
         *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(&tile[r][ch]);

@@ -27,6 +27,18 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
   gemm_q_tile<Q, BM>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
 }
 
+template <int BM>
+__global__ __launch_bounds__(256) void k_gemm_f32q(double* __restrict__ Lm, int64_t ldl,
+                                                   const float* __restrict__ ws,
+                                                   const GemmProb* __restrict__ probs, int nprobs,
+                                                   const double* __restrict__ part, int prec,
+                                                   int scale_mode, DevStatus* st) {
+  __shared__ __attribute__((aligned(16))) char pool[gemm_f32q_lds_bytes<BM>()];
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb P = probs[find_prob(probs, nprobs, w)];
+  gemm_f32q_tile<BM>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
+}
+
 template <typename T, int BM>
 __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t ldl,
                                                 const GemmProb* __restrict__ probs, int nprobs,
@@ -51,9 +63,9 @@ static void launch_gemm_bm(int prec, dim3 g, dim3 b, hipStream_t s, double* Lm, 
       hipLaunchKernelGGL((k_gemm_q<unsigned char, BM>), g, b, 0, s, Lm, ldl,
                          (const unsigned char*)ws, probs, nprobs, part, prec, scale_mode, st);
       break;
-    case F32:
-      hipLaunchKernelGGL((k_gemm_d<float, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
-                         scale_mode, st);
+    case F32:   // FP32 workspace copies
+      hipLaunchKernelGGL((k_gemm_f32q<BM>), g, b, 0, s, Lm, ldl, (const float*)ws, probs, nprobs,
+                         part, prec, scale_mode, st);
       break;
     default:
       hipLaunchKernelGGL((k_gemm_d<double, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,

@@ -93,6 +93,9 @@ hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, i
   if (prec == F16)
     hipLaunchKernelGGL(k_cast_max<_Float16>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs, njobs,
                        total_wg, part, prec, (_Float16*)ws);
+  else if (prec == F32)
+    hipLaunchKernelGGL(k_cast_max<float>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs, njobs,
+                       total_wg, part, prec, (float*)ws);
   else
     hipLaunchKernelGGL(k_cast_max<unsigned char>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs,
                        njobs, total_wg, part, prec, (unsigned char*)ws);
@@ -105,6 +108,9 @@ hipError_t launch_cast_fixup(const double* Lm, int64_t ldl, const CastJob* jobs,
   if (prec == F16)
     hipLaunchKernelGGL(k_cast_fixup<_Float16>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs, part,
                        prec, (_Float16*)ws, st);
+  else if (prec == F32)
+    hipLaunchKernelGGL(k_cast_fixup<float>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs, part,
+                       prec, (float*)ws, st);
   else
     hipLaunchKernelGGL(k_cast_fixup<unsigned char>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs,
                        part, prec, (unsigned char*)ws, st);

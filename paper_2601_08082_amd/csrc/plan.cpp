@@ -119,7 +119,7 @@ struct Builder {
 
   int64_t add_cast(std::vector<CastJob>& jobs, int prec, int64_t r, int64_t c, int rows, int cols,
                    std::pair<int, int> parts, int* ldq_out) {
-    int esz = prec == F16 ? 2 : 1;
+    int esz = prec == F32 ? 4 : prec == F16 ? 2 : 1;
     CastJob j{};
     j.src = off(r, c);
     j.rows = rows;
@@ -157,9 +157,15 @@ struct Builder {
     std::vector<MaxabsJob> mj;
     std::vector<CastJob> cj;
     std::vector<GemmProb> gp;
-    const bool quant = prec == F16 || prec == E4M3;
-    // FP16 with scale_mode 0: one pass casts at scale 1 and records the max-abs
-    const bool single_pass = quant && prec == F16 && t.scale_mode == 0 && !single_wg;
+    // FP32 operands of the multi-workgroup path are copied too (4 bytes per
+    // element and K-contiguous instead of the FP64 factor), always in one
+    // pass: FP32 blocks are never scaled up, so a block's scale is 1 unless
+    // its max-abs exceeds the FP32 range
+    const bool quant = prec == F16 || prec == E4M3 || (prec == F32 && !single_wg);
+    // FP16 with scale_mode 0 (and FP32): one pass casts at scale 1 and
+    // records the max-abs
+    const bool single_pass =
+        ((prec == F16 && t.scale_mode == 0) || prec == F32) && !single_wg;
     if (single_pass) with_parts = false;
     // Single pass: operands of the group with the same columns whose rows
     // overlap or touch share one scale-1 copy of the union of their rows (a
@@ -220,7 +226,7 @@ struct Builder {
         if (own) {
           v.dst = b.dst;   // sole user: cast again in place
         } else {
-          const int esz = prec == F16 ? 2 : 1;
+          const int esz = prec == F32 ? 4 : prec == F16 ? 2 : 1;
           ws_cursor = (size_t)rup((int64_t)ws_cursor, 256);
           v.dst = (int64_t)(ws_cursor / esz);
           ws_cursor += (size_t)o.rows * v.ldq * esz;
