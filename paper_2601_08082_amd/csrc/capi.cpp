@@ -109,7 +109,6 @@ static int launch_kind(const Launch& L) {
     case Launch::MAXABS: return MPCHOL_PROF_MAXABS;
     case Launch::POTRF: return MPCHOL_PROF_POTRF;
     case Launch::TRINV: return MPCHOL_PROF_TRINV;
-    case Launch::CASTFIX: return MPCHOL_PROF_MAXABS;
     case Launch::INVJOIN: return MPCHOL_PROF_TRINV;
     default: return MPCHOL_PROF_TRSM;
   }
@@ -171,8 +170,6 @@ static double launch_work(const Plan& P, const Launch& L) {
       const MaxabsJob& j = P.maxabs[L.first + i];
       w += (double)j.rows * j.cols * 8.0;
     }
-  } else if (L.kind == Launch::CASTFIX) {
-    for (int i = 0; i < L.count; i++) w += (double)P.casts[L.first + i].nparts * 8.0;
   } else if (L.kind == Launch::INVJOIN) {
     w = 2.0 * (double)(L.a1 - L.a2) * L.a2 * L.a1;   // the two products
   } else if (L.kind == Launch::POTRF || L.kind == Launch::TRINV) {
@@ -278,10 +275,6 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
         else
           e = launch_cast(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec, sm,
                           c->ws, c->dst, s);
-        break;
-      case Launch::CASTFIX:
-        e = launch_cast_fixup(L, ldl, P.d_casts + Lc.first, Lc.count, c->part, Lc.prec, c->ws,
-                              c->dst, s);
         break;
       case Launch::GEMM:
         e = launch_gemm(Lc.prec, Lc.tile, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count,
@@ -952,7 +945,7 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         build_plan(P, n_host[i], ldl_host[i], &t, true, tile);
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
-          if (L.kind == Launch::TRINV || L.kind == Launch::CASTFIX || L.kind == Launch::INVJOIN ||
+          if (L.kind == Launch::TRINV || L.kind == Launch::INVJOIN ||
               (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0) ||
               (L.kind == Launch::POTRF && L.a2 == 1)) {
             free_batch(c);

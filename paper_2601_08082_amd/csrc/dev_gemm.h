@@ -114,6 +114,32 @@ constexpr int gemm_q_lds_bytes() {
   return 2 * 2 * BM * (gemm_q_kbytes<BM>() + 16) + 256 * 8;
 }
 
+// EPV consecutive k of operand row `row` quantized on the fly from the FP64
+// factor (block at element offset src, scale 1 / inv_s), packed as the copy
+// would hold them: the path of a single-pass operand whose block scale is
+// not 1 (its scale-1 copy does not apply).  k >= K reads as 0.
+template <typename Q>
+__device__ inline uint4 direct_chunk(const double* __restrict__ Lm, int64_t ldl, int64_t src,
+                                     int row, int k0, int K, double inv_s, int prec) {
+  constexpr int EPV = 16 / (int)sizeof(Q);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < EPV; e++) {
+    const int k = k0 + e;
+    const double v = k < K ? Lm[src + row + (int64_t)k * ldl] * inv_s : 0.0;
+    uint32_t bits;
+    if constexpr (sizeof(Q) == 4) {
+      const float f = (float)v;
+      bits = __float_as_uint(f);
+    } else {
+      bits = encode_bits(v, prec);
+    }
+    constexpr int BITS = 8 * (int)sizeof(Q);
+    w[(e * BITS) / 32] |= (bits & (BITS == 32 ? 0xFFFFFFFFu : ((1u << BITS) - 1u))) << ((e * BITS) % 32);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // One output tile t of problem P (workgroup-level; lds = gemm_q_lds_bytes()).
 template <typename Q, int BM>
 __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
@@ -141,9 +167,13 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
 
   const int m0 = tm * BM, n0 = tn * BN;
-  // an operand whose block scale is not 1 reads its own scaled copy
-  const Q* __restrict__ X = ws + (isx == 1.0 ? P.x : P.x_alt);
-  const Q* __restrict__ Y = ws + (isy == 1.0 ? P.y : P.y_alt);
+  const Q* __restrict__ X = ws + P.x;
+  const Q* __restrict__ Y = ws + P.y;
+  // a single-pass operand (xsrc >= 0) whose block scale is not 1 is
+  // quantized from the factor on the way in (rare; its scale-1 copy does
+  // not apply)
+  const bool xdir = P.xsrc >= 0 && isx != 1.0, ydir = P.ysrc >= 0 && isy != 1.0;
+  const bool direct = xdir || ydir;   // uniform
   const int kv = (P.k + 15) & ~15;  // zero-padded K extent of the copies
   const int nk = (kv + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -155,14 +185,28 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   // step kt multiplies out of LDS), double-buffered LDS.
   uint4 rx[2][NV], ry[2][NV];
   auto gload = [&](int k0, uint4 (&vx)[NV], uint4 (&vy)[NV]) {
+    if (!direct) {
 #pragma unroll
-    for (int i = 0; i < NV; i++) {
-      int v = tid + 256 * i;
-      int row = v / CPR, ch = v % CPR;
-      int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
-      const int kc = min(k0 + ch * EPV, kv - EPV);
-      vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
-      vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      for (int i = 0; i < NV; i++) {
+        int v = tid + 256 * i;
+        int row = v / CPR, ch = v % CPR;
+        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+        const int kc = min(k0 + ch * EPV, kv - EPV);
+        vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+        vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; i++) {
+        int v = tid + 256 * i;
+        int row = v / CPR, ch = v % CPR;
+        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+        const int kc = min(k0 + ch * EPV, kv - EPV);
+        vx[i] = xdir ? direct_chunk<Q>(Lm, ldl, P.xsrc, gx, kc, P.k, isx, prec)
+                     : *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+        vy[i] = ydir ? direct_chunk<Q>(Lm, ldl, P.ysrc, gy, kc, P.k, isy, prec)
+                     : *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      }
     }
   };
   auto sstore = [&](int buf, int k0, const uint4 (&vx)[NV], const uint4 (&vy)[NV]) {
@@ -292,9 +336,12 @@ __device__ inline void gemm_f32q_tile(double* __restrict__ Lm, int64_t ldl,
   const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
 
   const int m0 = tm * BM, n0 = tn * BN;
-  // an operand whose block scale is not 1 reads its own scaled copy
-  const float* __restrict__ X = ws + (isx == 1.0 ? P.x : P.x_alt);
-  const float* __restrict__ Y = ws + (isy == 1.0 ? P.y : P.y_alt);
+  const float* __restrict__ X = ws + P.x;
+  const float* __restrict__ Y = ws + P.y;
+  // a block whose scale is not 1 is converted from the factor on the way in
+  // (rare: its max-abs exceeds the FP32 range)
+  const bool xdir = P.xsrc >= 0 && isx != 1.0, ydir = P.ysrc >= 0 && isy != 1.0;
+  const bool direct = xdir || ydir;   // uniform
   const int kv = (P.k + 15) & ~15;  // zero-padded K extent of the copies
   const int nk = (kv + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -304,14 +351,28 @@ __device__ inline void gemm_f32q_tile(double* __restrict__ Lm, int64_t ldl,
   // store; two register sets in flight, double-buffered LDS
   uint4 rx[2][NV], ry[2][NV];
   auto gload = [&](int k0, uint4 (&vx)[NV], uint4 (&vy)[NV]) {
+    if (!direct) {
 #pragma unroll
-    for (int i = 0; i < NV; i++) {
-      int v = tid + 256 * i;
-      int row = v / CPR, ch = v % CPR;
-      int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
-      const int kc = min(k0 + ch * 4, kv - 4);
-      vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
-      vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      for (int i = 0; i < NV; i++) {
+        int v = tid + 256 * i;
+        int row = v / CPR, ch = v % CPR;
+        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+        const int kc = min(k0 + ch * 4, kv - 4);
+        vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+        vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; i++) {
+        int v = tid + 256 * i;
+        int row = v / CPR, ch = v % CPR;
+        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+        const int kc = min(k0 + ch * 4, kv - 4);
+        vx[i] = xdir ? direct_chunk<float>(Lm, ldl, P.xsrc, gx, kc, P.k, isx, prec)
+                     : *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+        vy[i] = ydir ? direct_chunk<float>(Lm, ldl, P.ysrc, gy, kc, P.k, isy, prec)
+                     : *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      }
     }
   };
   auto sstore = [&](int buf, int k0, const uint4 (&vx)[NV], const uint4 (&vy)[NV]) {

@@ -172,66 +172,71 @@ __device__ inline void cast_tile(const double* __restrict__ Lm, int64_t ldl, con
   cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);  // 1/s exact
 }
 
-// Scale-1 cast that also records each tile's max |x| in the job's partials:
-// the first half of the single-pass quantization (scale_mode 0: a block whose
-// max |x| fits the format has scale 1), for every w = w0, w0 + stride, ...
-// < total (global tile index over the job list): the loads of the next tile
-// are in flight while this tile is encoded and stored.
+// Scale-1 cast that also records max |x| per work unit: the first half of the
+// single-pass quantization (a block whose max |x| fits the format has scale
+// 1).  Unit u of a job is a run of tpu tiles along tile row u % tiles_r
+// (chunk u / tiles_r) and writes one partial, part0 + row * units_r + chunk;
+// workgroup w0 takes units w0, w0 + stride, ... < total (global unit index
+// over the job list), with the next tile's loads in flight while this tile
+// is encoded and stored.
 template <typename Q>
 __device__ inline void cast_max_tiles(const double* __restrict__ Lm, int64_t ldl,
                                       const CastJob* __restrict__ jobs, int njobs, int w0,
                                       int stride, int total, double* __restrict__ part, int prec,
                                       Q* __restrict__ ws, char* lds) {
   double* red = reinterpret_cast<double*>(lds);
-  auto find = [&](int w) {
+  auto find = [&](int u) {
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
-      if (jobs[mid].wg_start <= w) lo = mid; else hi = mid - 1;
+      if (jobs[mid].wg_start <= u) lo = mid; else hi = mid - 1;
     }
     return lo;
   };
-  if (w0 >= total) return;
-  int j = find(w0);
-  double v[16], vn[16];
-  cast_load(Lm, ldl, jobs[j], w0 - jobs[j].wg_start, v);
-  for (int w = w0; w < total; w += stride) {
-    const int wn = min(w + stride, total - 1);   // past the end: a tile nobody uses
-    const int jn = find(wn);
-    cast_load(Lm, ldl, jobs[jn], wn - jobs[jn].wg_start, vn);
-    __builtin_amdgcn_sched_barrier(0);   // keep those loads here, ahead of this tile's work
+  // tile index (tr + tc * tiles_r) of tile i of unit u of job j
+  auto tile_of = [&](int j, int u, int i) {
     const CastJob& jb = jobs[j];
-    const int t = w - jb.wg_start;
-    __syncthreads();   // the previous tile's readers of the LDS tile are done
-    const double m = cast_finish<Q>(jb, t, v, 1.0, prec, ws, red, lds + 256 * 8, true);
-    // tile row-major, so that the tiles of a row range are contiguous
-    const int tr = t % jb.tiles_r, tc = t / jb.tiles_r;
-    if (threadIdx.x == 0) part[jb.part0 + tr * jb.tiles_c + tc] = m;
-#pragma unroll
-    for (int i = 0; i < 16; i++) v[i] = vn[i];
-    j = jn;
-  }
-}
-
-// Second half, one workgroup per job: the block max |x| from the tile partials
-// into part[jb.final_part]; a block whose scale is not 1 is cast again with it.
-template <typename Q>
-__device__ inline void cast_fixup_job(const double* __restrict__ Lm, int64_t ldl,
-                                      const CastJob& jb, double* __restrict__ part, int prec,
-                                      Q* __restrict__ ws, DevStatus* st, char* lds) {
-  double* red = reinterpret_cast<double*>(lds);
-  __syncthreads();
-  const double maxabs = reduce_parts(part, jb.part0, jb.nparts, red);
-  const bool bad = !(maxabs <= 1.7976931348623157e308);
-  if (threadIdx.x == 0) part[jb.final_part] = maxabs;
-  if (bad && threadIdx.x == 0) atomicOr(&st->nonfinite, 1u);
-  const double s = bad ? 1.0 : block_scale(maxabs, prec, 0);
-  if (s != 1.0) {
-    const int ntiles = jb.tiles_r * jb.tiles_c;
-    for (int t = 0; t < ntiles; t++) {
-      __syncthreads();
-      cast_core<Q>(Lm, ldl, jb, t, 1.0 / s, prec, ws, red, lds + 256 * 8, false);
+    const int ul = u - jb.wg_start;
+    const int tr = ul % jb.tiles_r, ch = ul / jb.tiles_r;
+    return tr + (ch * jb.tpu + i) * jb.tiles_r;
+  };
+  if (w0 >= total) return;
+  int u = w0, j = find(u), i = 0;
+  double v[16], vn[16];
+  cast_load(Lm, ldl, jobs[j], tile_of(j, u, 0), v);
+  double um = 0.0;
+  for (;;) {
+    const CastJob& jb = jobs[j];
+    const int ul = u - jb.wg_start;
+    const int tr = ul % jb.tiles_r, ch = ul / jb.tiles_r;
+    const int cnt = min(jb.tpu, jb.tiles_c - ch * jb.tpu);
+    const int t = tr + (ch * jb.tpu + i) * jb.tiles_r;
+    const bool unit_end = i + 1 >= cnt;
+    int un = u, in = i + 1, jn = j;
+    if (unit_end) {
+      un = u + stride;
+      in = 0;
     }
+    const bool more = un < total;
+    if (unit_end) {
+      un = min(un, total - 1);   // past the end: a tile nobody uses
+      jn = find(un);
+    }
+    cast_load(Lm, ldl, jobs[jn], tile_of(jn, un, in), vn);
+    __builtin_amdgcn_sched_barrier(0);   // keep those loads here, ahead of this tile's work
+    __syncthreads();   // the previous tile's readers of the LDS tile are done
+    um = fmax(um, cast_finish<Q>(jb, t, v, 1.0, prec, ws, red, lds + 256 * 8, true));
+    if (unit_end) {
+      const int units_r = (jb.tiles_c + jb.tpu - 1) / jb.tpu;
+      if (threadIdx.x == 0) part[jb.part0 + tr * units_r + ch] = um;
+      um = 0.0;
+    }
+    if (!more) break;
+#pragma unroll
+    for (int q = 0; q < 16; q++) v[q] = vn[q];
+    u = un;
+    i = in;
+    j = jn;
   }
 }
 

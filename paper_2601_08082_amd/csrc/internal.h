@@ -46,7 +46,8 @@ struct CastJob {
   int32_t tiles_r;   // 64-row tiles
   int32_t tiles_c;   // 64-col tiles over ldq
   int32_t wg_start;
-  int32_t final_part;  // single-pass cast: slot of the block's max |x| (else -1)
+  int32_t tpu;       // single-pass cast: 64 x 64 tiles per work unit, a run of
+                     // one tile row with one max-abs partial (else 0)
 };
 
 // One GEMM problem of a grouped launch:  C(m x n) -= sx*sy * X(m x k) Y(n x k)^T
@@ -63,9 +64,10 @@ struct GemmProb {
   int32_t tiles_m, tiles_n;
   int32_t tile_start;  // prefix sum of tiles over the problem list
   int32_t pad;
-  // F16/E4M3: copies to read instead of x / y when that operand's block scale
-  // is not 1 (equal to x / y unless a scale-1 copy is shared between problems)
-  int64_t x_alt, y_alt;
+  // Single-pass copies (scale 1, maybe shared between problems): element
+  // offsets of the operand blocks in the factor, quantized from there when a
+  // block's scale is not 1; -1 for copies cast with their block scale.
+  int64_t xsrc, ysrc;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -78,13 +80,11 @@ hipError_t launch_maxabs(const double* Lm, int64_t ldl, const MaxabsJob* jobs, i
 hipError_t launch_cast(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                        int total_wg, const double* part, int prec, int scale_mode, void* ws,
                        DevStatus* st, hipStream_t s);
-// Single-pass quantization (FP16, scale_mode 0): scale-1 cast with per-tile
-// max-abs partials, then one workgroup per job finalizes the block max-abs
-// and re-casts the rare block whose scale is not 1.
+// Single-pass quantization (FP16 with scale_mode 0, FP32): scale-1 cast that
+// records one max-abs partial per work unit (total_wg = units); the GEMM
+// reduces an operand's partials to its block scale.
 hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                            int total_wg, double* part, int prec, void* ws, hipStream_t s);
-hipError_t launch_cast_fixup(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
-                             double* part, int prec, void* ws, DevStatus* st, hipStream_t s);
 hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* ws,
                        const GemmProb* probs, int nprobs, int total_tiles, const double* part,
                        int scale_mode, DevStatus* st, hipStream_t s);

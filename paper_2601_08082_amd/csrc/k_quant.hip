@@ -75,15 +75,6 @@ __global__ __launch_bounds__(256) void k_cast_max(const double* __restrict__ Lm,
   cast_max_tiles<Q>(Lm, ldl, jobs, njobs, blockIdx.x, gridDim.x, total, part, prec, ws, pool);
 }
 
-template <typename Q>
-__global__ __launch_bounds__(256) void k_cast_fixup(const double* __restrict__ Lm, int64_t ldl,
-                                                    const CastJob* __restrict__ jobs,
-                                                    double* __restrict__ part, int prec,
-                                                    Q* __restrict__ ws, DevStatus* st) {
-  __shared__ __attribute__((aligned(16))) char pool[cast_lds_bytes<Q>()];
-  cast_fixup_job<Q>(Lm, ldl, jobs[blockIdx.x], part, prec, ws, st, pool);
-}
-
 hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
                            int total_wg, double* part, int prec, void* ws, hipStream_t s) {
   if (njobs <= 0 || total_wg <= 0) return hipSuccess;
@@ -99,21 +90,6 @@ hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, i
   else
     hipLaunchKernelGGL(k_cast_max<unsigned char>, dim3(g), dim3(256), 0, s, Lm, ldl, jobs,
                        njobs, total_wg, part, prec, (unsigned char*)ws);
-  return hipGetLastError();
-}
-
-hipError_t launch_cast_fixup(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,
-                             double* part, int prec, void* ws, DevStatus* st, hipStream_t s) {
-  if (njobs <= 0) return hipSuccess;
-  if (prec == F16)
-    hipLaunchKernelGGL(k_cast_fixup<_Float16>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs, part,
-                       prec, (_Float16*)ws, st);
-  else if (prec == F32)
-    hipLaunchKernelGGL(k_cast_fixup<float>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs, part,
-                       prec, (float*)ws, st);
-  else
-    hipLaunchKernelGGL(k_cast_fixup<unsigned char>, dim3(njobs), dim3(256), 0, s, Lm, ldl, jobs,
-                       part, prec, (unsigned char*)ws, st);
   return hipGetLastError();
 }
 

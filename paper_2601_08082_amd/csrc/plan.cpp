@@ -132,7 +132,7 @@ struct Builder {
     j.nparts = parts.second;
     j.tiles_r = (int)cdiv(rows, 64);
     j.tiles_c = (int)cdiv(j.ldq, 64);
-    j.final_part = -1;
+    j.tpu = 0;
     jobs.push_back(j);
     P.stats.cast_bytes += (double)rows * cols * (8.0 + esz);
     *ldq_out = j.ldq;
@@ -170,14 +170,14 @@ struct Builder {
     // Single pass: operands of the group with the same columns whose rows
     // overlap or touch share one scale-1 copy of the union of their rows (a
     // SYRK's sub-products read every row of its operand once per recursion
-    // level).  Each operand keeps its own block scale: a fix-up job reduces
-    // the copy's 64 x 64 tile maxima over the operand's rows and, when the
-    // scale is not 1, casts the operand again into a copy of its own that
-    // the GEMM then reads.  Sharing needs operand rows on 64-row tile
+    // level).  Each operand keeps its own block scale: the GEMM reduces the
+    // copy's 64 x 64 tile maxima over the operand's rows, and when that
+    // scale is not 1 it quantizes the operand from the factor instead of
+    // reading the copy.  Sharing needs operand rows on 64-row tile
     // boundaries of the union, so the tiles reduced are exactly the
     // operand's; an operand that is not aligned gets a copy of its own.
-    std::vector<CastJob> views;
-    std::vector<int64_t> view_base_dst;   // the operand's rows in the shared copy
+    struct OpView { int64_t dst, src; int part0, nparts, ldq; };
+    std::vector<OpView> views;
     std::vector<int> node_x(nodes.size(), -1), node_y(nodes.size(), -1);
     if (single_pass) {
       struct Opd { int64_t r, c; int rows, k; };
@@ -201,39 +201,30 @@ struct Builder {
         int ldq = 0;
         add_cast(cj, prec, r, c, rows, k, {0, 0}, &ldq);
         CastJob& j = cj.back();
-        j.part0 = (int)part_cursor;   // tile maxima, tile row-major
-        j.nparts = j.tiles_r * j.tiles_c;
+        // work units of tpu tiles along a tile row, one partial each (unit
+        // row-major), so that an operand's rows are a contiguous range of at
+        // most about 1024 partials
+        j.tpu = (int)std::min<int64_t>(j.tiles_c, cdiv((int64_t)j.tiles_r * j.tiles_c, 1024));
+        j.part0 = (int)part_cursor;
+        j.nparts = j.tiles_r * (int)cdiv(j.tiles_c, j.tpu);
         part_cursor += j.nparts;
         base_row.resize(cj.size(), 0);
         base_row.back() = r;
         return (int)cj.size() - 1;
       };
-      auto make_view = [&](int oi, int bi, bool own) {
+      auto make_view = [&](int oi, int bi) {
         const Opd& o = ops[oi];
         const CastJob& b = cj[bi];
         const int64_t dr = o.r - base_row[bi];
-        CastJob v{};
+        OpView v{};
+        v.dst = b.dst + dr * b.ldq;
         v.src = off(o.r, o.c);
-        v.rows = o.rows;
-        v.cols = o.k;
+        const int units_r = (int)cdiv(b.tiles_c, b.tpu);   // units per tile row
+        v.part0 = b.part0 + (int)(dr / 64) * units_r;
+        v.nparts = (int)(cdiv(dr + o.rows, 64) - dr / 64) * units_r;
         v.ldq = b.ldq;
-        v.tiles_r = (int)cdiv(o.rows, 64);
-        v.tiles_c = b.tiles_c;
-        v.part0 = b.part0 + (int)(dr / 64) * b.tiles_c;
-        v.nparts = (int)(cdiv(dr + o.rows, 64) - dr / 64) * b.tiles_c;
-        v.final_part = (int)part_cursor++;
-        const int64_t shared_dst = b.dst + dr * b.ldq;
-        if (own) {
-          v.dst = b.dst;   // sole user: cast again in place
-        } else {
-          const int esz = prec == F32 ? 4 : prec == F16 ? 2 : 1;
-          ws_cursor = (size_t)rup((int64_t)ws_cursor, 256);
-          v.dst = (int64_t)(ws_cursor / esz);
-          ws_cursor += (size_t)o.rows * v.ldq * esz;
-        }
         opd_view[oi] = (int)views.size();
         views.push_back(v);
-        view_base_dst.push_back(shared_dst);
       };
       for (auto& kv : cls) {
         std::vector<int>& idx = kv.second;
@@ -274,7 +265,7 @@ struct Builder {
             }
             if (ok) {
               const int bi = make_base(s0, kv.first.first, (int)(s1 - s0), kv.first.second);
-              for (int oi : aligned) make_view(oi, bi, false);
+              for (int oi : aligned) make_view(oi, bi);
             } else {
               other.insert(other.end(), aligned.begin(), aligned.end());
             }
@@ -282,7 +273,7 @@ struct Builder {
           for (int oi : other) {
             if (opd_view[oi] >= 0) continue;
             const int bi = make_base(ops[oi].r, ops[oi].c, ops[oi].rows, ops[oi].k);
-            make_view(oi, bi, true);
+            make_view(oi, bi);
           }
           i = j;
         }
@@ -310,18 +301,18 @@ struct Builder {
       g.ypart0 = py.first;
       g.ynparts = py.second;
       if (single_pass) {
-        const CastJob& vx = views[node_x[ni]];
-        const CastJob& vy = views[node_y[ni]];
-        g.x = view_base_dst[node_x[ni]];
-        g.x_alt = vx.dst;
+        const OpView& vx = views[node_x[ni]];
+        const OpView& vy = views[node_y[ni]];
+        g.x = vx.dst;
+        g.xsrc = vx.src;
         g.ldx = vx.ldq;
-        g.xpart0 = vx.final_part;
-        g.xnparts = 1;
-        g.y = view_base_dst[node_y[ni]];
-        g.y_alt = vy.dst;
+        g.xpart0 = vx.part0;
+        g.xnparts = vx.nparts;
+        g.y = vy.dst;
+        g.ysrc = vy.src;
         g.ldy = vy.ldq;
-        g.ypart0 = vy.final_part;
-        g.ynparts = 1;
+        g.ypart0 = vy.part0;
+        g.ynparts = vy.nparts;
       } else if (quant) {
         int ldx = 0, ldy = 0;
         g.x = add_cast(cj, prec, nd.xr, nd.xc, nd.m, nd.k, px, &ldx);
@@ -333,13 +324,11 @@ struct Builder {
           g.y = add_cast(cj, prec, nd.yr, nd.yc, nd.n, nd.k, py, &ldy);
           g.ldy = ldy;
         }
-        g.x_alt = g.x;
-        g.y_alt = g.y;
+        g.xsrc = g.ysrc = -1;
       } else {
         g.x = off(nd.xr, nd.xc);
         g.y = off(nd.yr, nd.yc);
-        g.x_alt = g.x;
-        g.y_alt = g.y;
+        g.xsrc = g.ysrc = -1;
         g.ldx = g.ldy = (int)ldl;
       }
       double fl = nd.lower ? (double)nd.m * (nd.m + 1) * nd.k : 2.0 * nd.m * nd.n * nd.k;
@@ -367,19 +356,11 @@ struct Builder {
       int wg = 0;
       for (auto& j : cj) {
         j.wg_start = wg;
-        wg += j.tiles_r * j.tiles_c;
+        wg += single_pass ? j.tiles_r * (int)cdiv(j.tiles_c, j.tpu) : j.tiles_r * j.tiles_c;
       }
       L.total = wg;
       P.casts.insert(P.casts.end(), cj.begin(), cj.end());
       P.launches.push_back(L);
-      if (single_pass) {
-        Launch F{Launch::CASTFIX, prec};
-        F.first = (int)P.casts.size();
-        F.count = (int)views.size();
-        F.total = F.count;
-        P.casts.insert(P.casts.end(), views.begin(), views.end());
-        P.launches.push_back(F);
-      }
     }
     {
       Launch L{Launch::GEMM, prec};

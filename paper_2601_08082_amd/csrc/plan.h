@@ -12,7 +12,7 @@
 namespace mpc {
 
 struct Launch {
-  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, CASTFIX, INVJOIN } kind;
+  enum Kind { POTRF, TRSM, MAXABS, CAST, GEMM, TRINV, INVJOIN } kind;
   int prec;
   int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // POTRF / TRINV: i0, m (POTRF a2 = 1: also
                                           // the inverse); TRSM: r0, m, c0, k;
