@@ -468,18 +468,53 @@ __global__ __launch_bounds__(256) void k_resid_reduce(int64_t n, int nrhs,
                                                       const double* __restrict__ colp,
                                                       const double* __restrict__ B, int64_t ldb,
                                                       double* __restrict__ R, int64_t ldr) {
+  // Block row I sums nrow row-chunk partials and ncol transposed-tile partials
+  // per output.  G threads share an output (terms g, g + G, ...), each with
+  // four loads in flight, then the G sums are added in g order: the order is
+  // fixed, so the result is deterministic.
+  constexpr int NE = NB * NR;
+  constexpr int G = NE >= 256 ? 1 : 256 / NE;
+  __shared__ double red[256];
   const int64_t I = blockIdx.x;
   const int nblk = (int)((n + NB - 1) / NB);
   const int nch = (nblk + RCH - 1) / RCH;
   const int64_t i0 = I * NB;
   const int ni = (int)min((int64_t)NB, n - i0);
-  for (int idx = threadIdx.x; idx < NB * NR; idx += 256) {
-    const int rr = idx % NB, c = idx / NB;
-    if (rr >= ni || c >= nrhs) continue;
-    double t = 0.0;
-    for (int64_t ch = 0; ch * RCH <= I; ch++) t += rowp[((int64_t)I * nch + ch) * NB * NR + idx];
-    for (int64_t Jp = I + 1; Jp < nblk; Jp++) t += colp[tri_index(Jp, I) * NB * NR + idx];
-    R[(i0 + rr) + (int64_t)c * ldr] = B[(i0 + rr) + (int64_t)c * ldb] - t;
+  const int nrow = (int)(I / RCH) + 1, nterm = nrow + (nblk - 1 - (int)I);
+  auto term = [&](int q, int idx) -> const double* {
+    return q < nrow ? &rowp[((int64_t)I * nch + q) * NE + idx]
+                    : &colp[tri_index(I + 1 + (q - nrow), I) * NE + idx];
+  };
+  for (int base = 0; base < NE; base += 256 / G) {
+    const int idx = base + (int)threadIdx.x % (256 / G), g = (int)threadIdx.x / (256 / G);
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    if (idx < NE) {
+      int q = g;
+      for (; q + 3 * G < nterm; q += 4 * G) {
+        const double a0 = *term(q, idx), a1 = *term(q + G, idx);
+        const double a2 = *term(q + 2 * G, idx), a3 = *term(q + 3 * G, idx);
+        t[0] += a0;
+        t[1] += a1;
+        t[2] += a2;
+        t[3] += a3;
+      }
+      if (q < nterm) t[0] += *term(q, idx);
+      if (q + G < nterm) t[1] += *term(q + G, idx);
+      if (q + 2 * G < nterm) t[2] += *term(q + 2 * G, idx);
+    }
+    const double sum = (t[0] + t[1]) + (t[2] + t[3]);
+    if (G > 1) {
+      red[threadIdx.x] = sum;
+      __syncthreads();
+    }
+    if (g == 0 && idx < NE) {
+      double tot = sum;
+      for (int h = 1; h < G; h++) tot += red[h * (256 / G) + idx];
+      const int rr = idx % NB, c = idx / NB;
+      if (rr < ni && c < nrhs)
+        R[(i0 + rr) + (int64_t)c * ldr] = B[(i0 + rr) + (int64_t)c * ldb] - tot;
+    }
+    if (G > 1) __syncthreads();
   }
 }
 
