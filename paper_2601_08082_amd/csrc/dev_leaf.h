@@ -54,6 +54,32 @@ __device__ inline float qdiv(float a, float b, float y) {
   return fmaf(r, y, q0);
 }
 
+// For d >= 2^-767 (normal, finite): l = RN(sqrt(d)) and y = RN(1 / l).  The
+// square root refines the hardware reciprocal square root by Goldschmidt
+// steps (correctly rounded in this range); the reciprocal starts from the
+// refined half-reciprocal, takes two Newton steps and a Markstein step, which
+// is exact except when l's significand is all ones: then it lands one ulp
+// low, and that case is raised back by the exact product y (1 + 2^-52).
+__device__ inline void sqrt_rcp(double d, double& l, double& y) {
+  const double r0 = __builtin_amdgcn_rsq(d);
+  double g = d * r0, h = 0.5 * r0;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double e = fma(-g, g, d);
+  g = fma(e, h, g);
+  e = fma(-g, g, d);
+  g = fma(e, h, g);
+  const double y0 = 2.0 * h;
+  double t = fma(-g, y0, 1.0);
+  const double y1 = fma(y0, t, y0);
+  t = fma(-g, y1, 1.0);
+  const double y2 = fma(y1, t, y1);
+  const bool all_ones = (__double_as_longlong(g) & 0xFFFFFFFFFFFFFll) == 0xFFFFFFFFFFFFFll;
+  l = g;
+  y = all_ones ? y2 * (1.0 + 0x1p-52) : y2;
+}
+
 // ---------------------------------------------------------------- POTRF
 // A(i0:i0+m, i0:i0+m) <- chol, lower, m <= 128, whole block in LDS.  The block
 // is padded to mp = 16 ceil(m / 16) with an identity extension (pivots 1,
@@ -110,9 +136,21 @@ __device__ __attribute__((always_inline)) inline void potrf_leaf_body(
         const int j = p + jj;
         const T d = lane_bcast(x[jj], jj);
         if (bad == 0 && j < m && !(d > (T)0 && isfinite((double)d))) bad = j + 1;
-        const T ljj = sqrt(d);
-        const T y = (T)1 / ljj;
-        const T q = qdiv(x[jj], ljj, y);
+        T ljj, q;
+        if constexpr (sizeof(T) == 8) {
+          // d is uniform: a pivot below 2^-767 (subnormal included) is taken
+          // as d 2^256, whose root is l 2^128; x is scaled by the same 2^128
+          // (exact), so the quotient is x / l itself
+          const int dhi = (int)(__double_as_longlong(d) >> 32);
+          const int sc = dhi < 0x10000000 ? 128 : 0;
+          double ls, ys;
+          sqrt_rcp(__builtin_amdgcn_ldexp(d, 2 * sc), ls, ys);
+          ljj = __builtin_amdgcn_ldexp(ls, -sc);
+          q = qdiv(__builtin_amdgcn_ldexp(x[jj], sc), ls, ys);
+        } else {
+          ljj = sqrt(d);
+          q = qdiv(x[jj], ljj, (T)1 / ljj);
+        }
         x[jj] = lane == jj ? ljj : q;
 #pragma unroll
         for (int kk = jj + 1; kk < PW; kk++) {
