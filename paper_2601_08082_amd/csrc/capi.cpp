@@ -260,10 +260,8 @@ static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStre
                          c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
         break;
       case Launch::INVJOIN:
-        // scratch: the slot after the last one
         e = launch_inv_join(L, ldl, Lc.a0, (int)Lc.a1, (int)Lc.a2,
-                            c->inv + (size_t)Lc.first * kInvLd * kInvLd, kInvLd,
-                            c->inv + (size_t)P.ninv * kInvLd * kInvLd, s);
+                            c->inv + (size_t)Lc.first * kInvLd * kInvLd, kInvLd, s);
         break;
       case Launch::MAXABS:
         e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
@@ -638,7 +636,7 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
     if (c->inv) HIPCHK(hipFree(c->inv));
     c->inv = nullptr;
     c->ninv = 0;
-    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kInvLd * kInvLd * (size_t)(P->ninv + 1)));
+    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kInvLd * kInvLd * (size_t)P->ninv));
     c->ninv = P->ninv;
   }
   if (info) HIPCHK(hipEventRecord(c->ev0, s));

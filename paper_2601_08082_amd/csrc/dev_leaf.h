@@ -508,6 +508,66 @@ __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64
   }
 }
 
+// One 16 x 16 tile (row strip ti, column block tc) of the off-diagonal block
+// of a joined inverse, Y21 = -Y2 (L21 Y1), Y1 (m1 x m1) and Y2 (m2 x m2) lower
+// triangular, m1, m2 <= 128, 256 threads.  The strip needs the rows of
+// T = L21 Y1 up to its own last row (Y2 is lower), and in column block tc
+// only Y1's rows from 16 tc on are nonzero: the waves form those T tiles
+// (FP64 MFMA, the skipped products are exact zeros), keep them in LDS, and
+// wave 0 multiplies the strip of Y2 into them in the same order as a full
+// product would.
+__device__ inline void inv_join_tile(const double* __restrict__ L21, int64_t ldl,
+                                     const double* __restrict__ Y1, const double* __restrict__ Y2,
+                                     double* __restrict__ Y21, int ldy, int m1, int m2, int ti,
+                                     int tc, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nk = ti + 1;                 // T row blocks 0 .. ti
+  const int q0 = 16 * tc;                // first nonzero row of Y1's column block
+  const int c = min(16 * tc + (lane & 15), m1 - 1);
+  for (int kb = wave; kb < nk; kb += 4) {
+    const int r = min(16 * kb + (lane & 15), m2 - 1);
+    double av[KL / 4], bv[KL / 4];
+#pragma unroll
+    for (int q = 0; q < KL / 4; q++) {
+      const int kk = q0 + 4 * q + (lane >> 4), kc = min(kk, m1 - 1);
+      const double a = L21[r + (int64_t)kc * ldl];
+      const double b = Y1[kc + (int64_t)c * ldy];
+      av[q] = kk < m1 ? a : 0.0;
+      bv[q] = kk < m1 ? b : 0.0;
+    }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KL / 4; q++)
+      if (q0 + 4 * q < m1) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+    // T(16 kb + row, col) at lds[(16 kb + row) * 17 + col]
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++)
+      lds[(16 * kb + (lane >> 4) + 4 * rr) * 17 + (lane & 15)] = acc[rr];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int r = min(16 * ti + (lane & 15), m2 - 1);
+    double av[KL / 4], bv[KL / 4];
+#pragma unroll
+    for (int q = 0; q < KL / 4; q++) {
+      const int kk = 4 * q + (lane >> 4), kc = min(kk, m2 - 1);
+      const double a = Y2[r + (int64_t)kc * ldy];
+      const bool in = kk < 16 * nk && kk < m2;
+      av[q] = in ? a : 0.0;
+      bv[q] = in ? lds[min(kk, 16 * nk - 1) * 17 + (lane & 15)] : 0.0;
+    }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KL / 4; q++)
+      if (4 * q < 16 * nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++) {
+      const int row = 16 * ti + (lane >> 4) + 4 * rr, col = 16 * tc + (lane & 15);
+      if (row < m2 && col < m1) Y21[row + (int64_t)col * ldy] = -acc[rr];
+    }
+  }
+}
+
 // C(M x N) = alpha A(M x K) B(K x N), all column-major FP64, M, N, K <= 128:
 // one wave per 16 x 16 output tile (blockIdx.x = tile), FP64 MFMA.  Used to
 // join two leaf inverses into the inverse of their parent block.

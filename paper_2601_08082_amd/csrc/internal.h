@@ -101,7 +101,7 @@ hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double
 hipError_t launch_potrf_inv(double* Lm, int64_t ldl, int64_t i0, int m, DevStatus* st, double* Y,
                            int ldy, hipStream_t s);
 hipError_t launch_inv_join(const double* Lm, int64_t ldl, int64_t i0, int m, int m1, double* Y,
-                           int ldy, double* T, hipStream_t s);
+                           int ldy, hipStream_t s);
 hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
                            const double* Y, int ldy, hipStream_t s);
 hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64_t m,

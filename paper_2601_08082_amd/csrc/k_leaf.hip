@@ -68,6 +68,15 @@ __global__ __launch_bounds__(256) void k_trsm_inv(double* __restrict__ Lm, int64
   trsm_inv_rows<NCB>(Lm, ldl, r0, m, c0, k, Y, ldy, blockIdx.x);
 }
 
+__global__ __launch_bounds__(256) void k_inv_join(const double* __restrict__ L21, int64_t ldl,
+                                                  const double* __restrict__ Y1,
+                                                  const double* __restrict__ Y2,
+                                                  double* __restrict__ Y21, int ldy, int m1,
+                                                  int m2) {
+  __shared__ double t[KL * 17];
+  inv_join_tile(L21, ldl, Y1, Y2, Y21, ldy, m1, m2, blockIdx.x, blockIdx.y, t);
+}
+
 __global__ __launch_bounds__(64) void k_small_gemm(double* __restrict__ C, int ldc,
                                                    const double* __restrict__ A, int64_t lda,
                                                    const double* __restrict__ B, int ldb, int M,
@@ -120,15 +129,14 @@ hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64
 }
 
 hipError_t launch_inv_join(const double* Lm, int64_t ldl, int64_t i0, int m, int m1, double* Y,
-                           int ldy, double* T, hipStream_t s) {
+                           int ldy, hipStream_t s) {
   // Y = [Y1 0; Y21 Y2] with Y21 = -Y2 (L21 Y1), L21 = L(i0+m1 : i0+m, i0 : i0+m1)
   const int m2 = m - m1;
   if (m1 <= 0 || m2 <= 0 || m1 > KL || m2 > KL) return hipErrorInvalidValue;
   const double* L21 = Lm + (i0 + m1) + i0 * ldl;
-  const dim3 g((unsigned)(((m2 + 15) / 16) * ((m1 + 15) / 16)));
-  hipLaunchKernelGGL(k_small_gemm, g, dim3(64), 0, s, T, KL, L21, ldl, Y, ldy, m2, m1, m1, 1.0);
-  hipLaunchKernelGGL(k_small_gemm, g, dim3(64), 0, s, Y + m1, ldy, Y + m1 + (int64_t)m1 * ldy,
-                     (int64_t)ldy, T, KL, m2, m1, m2, -1.0);
+  const dim3 g((unsigned)((m2 + 15) / 16), (unsigned)((m1 + 15) / 16));
+  hipLaunchKernelGGL(k_inv_join, g, dim3(256), 0, s, L21, ldl, Y, Y + m1 + (int64_t)m1 * ldy,
+                     Y + m1, ldy, m1, m2);
   return hipGetLastError();
 }
 
