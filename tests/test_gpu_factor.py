@@ -93,6 +93,26 @@ def test_integer_factor_bitwise(M, ctx, n, ti):
     assert np.max(np.abs(np.tril(L[:n, :n]) - L0)) <= 1e-13 * np.max(np.abs(L0))
 
 
+@pytest.mark.parametrize("n,e", [(7, -772), (130, -780), (300, -900)])
+def test_tiny_pivots_scale_exactly(M, ctx, n, e):
+    """Pivots below 2^-767 take the rescaled square-root path of the leaf
+    POTRF (the sizes and scales put them below, across and far below that
+    bound): A = 2^e L0 L0^T has the factor 2^(e/2) L0 bit for bit with the
+    substitution leaf TRSM, and within FP64 rounding with the leaf inverses."""
+    import dataclasses
+    print(f"[gpu] tiny pivots n={n} e={e}", flush=True)
+    L0, A = _integer_L0(n, seed=3000 + n)
+    As = np.asfortranarray(np.ldexp(A, e))
+    Ls0 = np.ldexp(L0, e // 2)
+    t = M.Tree(leaf=64, offdiag=[M.F64])
+    L, info = _gpu_factor(M, ctx, As, n, dataclasses.replace(t, leaf_trsm=1))
+    assert info["status"] == M.OK, info
+    np.testing.assert_array_equal(np.tril(L[:n, :n]), Ls0)
+    L, info = _gpu_factor(M, ctx, As, n, t)
+    assert info["status"] == M.OK, info
+    assert np.max(np.abs(np.tril(L[:n, :n]) - Ls0)) <= 1e-13 * np.max(np.abs(Ls0))
+
+
 @pytest.mark.parametrize("n,leaf", [(5, 4), (100, 37), (300, 64), (700, 128), (1111, 200),
                                     (2600, 256), (3001, 128)])
 def test_leaf_inverse_trsm_vs_substitution(M, ctx, n, leaf):
