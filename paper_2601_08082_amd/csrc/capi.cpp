@@ -59,6 +59,10 @@ struct mpchol_ctx_s {
   double* npart = nullptr;    // norm partials (device)
   double* hnpart = nullptr;   // norm partials (pinned host)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // copy of A's rows below the top-level A11 into L, overlapped with A11's
+  // factorization
+  hipStream_t side = nullptr;
+  hipEvent_t ev_in = nullptr, ev_copy = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
   // per-launch-class event timing (mpchol_profile)
   uint32_t prof_mask = 0;
@@ -235,9 +239,13 @@ static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, 
   return 0;
 }
 
-static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStream_t s) {
+// wait_at >= 0: the stream waits for wait_ev before launch wait_at.
+static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStream_t s,
+                    int wait_at = -1, hipEvent_t wait_ev = nullptr) {
   const int sm = P.tree.scale_mode;
-  for (const Launch& Lc : P.launches) {
+  for (size_t li = 0; li < P.launches.size(); li++) {
+    const Launch& Lc = P.launches[li];
+    if ((int)li == wait_at) HIPCHK(hipStreamWaitEvent(s, wait_ev, 0));
     hipError_t e = hipSuccess;
     const int pk = c->prof_mask ? prof_begin(c, launch_kind(Lc), launch_work(P, Lc), s) : -1;
     switch (Lc.kind) {
@@ -578,6 +586,9 @@ int mpchol_create(mpchol_ctx* ctx, int device) {
                        hipHostMallocDefault));
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
+  HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
   *ctx = c.release();
   return 0;
 }
@@ -603,6 +614,9 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->hst) (void)hipHostFree(c->hst);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+  if (c->side) (void)hipStreamDestroy(c->side);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   free_batch(c);
   if (c->bt.cap) (void)hipStreamDestroy(c->bt.cap);
@@ -641,8 +655,20 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
   }
   if (info) HIPCHK(hipEventRecord(c->ev0, s));
   HIPCHK(launch_status_init(c->dst, s));
-  if (L != A) HIPCHK(launch_copy_lower(A, lda, L, ldl, n, s));
-  r = run_plan(c, *P, L, ldl, s);
+  if (L != A && P->first_outer > 0) {
+    // A11 on the caller's stream; the rows below it on the side stream, which
+    // the caller's stream joins before the first launch that reads them
+    const int64_t n1 = P->split1;
+    HIPCHK(launch_copy_lower_rows(A, lda, L, ldl, 0, n1, 0, n1, s));
+    HIPCHK(hipEventRecord(c->ev_in, s));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_in, 0));
+    HIPCHK(launch_copy_lower_rows(A, lda, L, ldl, 0, n, n1, n, c->side));
+    HIPCHK(hipEventRecord(c->ev_copy, c->side));
+    r = run_plan(c, *P, L, ldl, s, P->first_outer, c->ev_copy);
+  } else {
+    if (L != A) HIPCHK(launch_copy_lower(A, lda, L, ldl, n, s));
+    r = run_plan(c, *P, L, ldl, s);
+  }
   if (r) return r;
   HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   if (!info) return 0;

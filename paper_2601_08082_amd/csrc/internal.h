@@ -75,6 +75,9 @@ struct GemmProb {
 hipError_t launch_status_init(DevStatus* st, hipStream_t s);
 hipError_t launch_copy_lower(const double* A, int64_t lda, double* L, int64_t ldl, int64_t n,
                              hipStream_t s);
+// L(i, j) = A(i, j) for c0 <= j < c1 and max(j, rb) <= i < re.
+hipError_t launch_copy_lower_rows(const double* A, int64_t lda, double* L, int64_t ldl, int64_t c0,
+                                  int64_t c1, int64_t rb, int64_t re, hipStream_t s);
 hipError_t launch_maxabs(const double* Lm, int64_t ldl, const MaxabsJob* jobs, int njobs,
                          int total_wg, double* part, hipStream_t s);
 hipError_t launch_cast(const double* Lm, int64_t ldl, const CastJob* jobs, int njobs,

@@ -23,14 +23,24 @@ __global__ void k_ticket_reset(DevStatus* st) {
   if (threadIdx.x < 4) st->ticket[threadIdx.x] = 0u;
 }
 
-// L(i, j) = A(i, j) for i >= j.  One workgroup per column.
+// L(i, j) = A(i, j) for j = c0 + blockIdx.x and max(j, rb) <= i < re (a
+// lower-triangle band of rows).  One workgroup per column, four independent
+// loads per thread in flight.
 __global__ __launch_bounds__(256) void k_copy_lower(const double* __restrict__ A, int64_t lda,
                                                     double* __restrict__ L, int64_t ldl,
-                                                    int64_t n) {
-  int64_t j = (int64_t)blockIdx.x;
+                                                    int64_t c0, int64_t rb, int64_t re) {
+  const int64_t j = c0 + (int64_t)blockIdx.x;
   const double* a = A + j * lda;
   double* l = L + j * ldl;
-  for (int64_t i = j + threadIdx.x; i < n; i += 256) l[i] = a[i];
+  int64_t i = max(j, rb) + threadIdx.x;
+  for (; i + 768 < re; i += 1024) {
+    const double v0 = a[i], v1 = a[i + 256], v2 = a[i + 512], v3 = a[i + 768];
+    l[i] = v0;
+    l[i + 256] = v1;
+    l[i + 512] = v2;
+    l[i + 768] = v3;
+  }
+  for (; i < re; i += 256) l[i] = a[i];
 }
 
 // Partial max |x| over a column range of each job's block.  Non-finite values
@@ -105,8 +115,14 @@ hipError_t launch_ticket_reset(DevStatus* st, hipStream_t s) {
 
 hipError_t launch_copy_lower(const double* A, int64_t lda, double* L, int64_t ldl, int64_t n,
                              hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_lower, dim3((unsigned)n), dim3(256), 0, s, A, lda, L, ldl, n);
+  return launch_copy_lower_rows(A, lda, L, ldl, 0, n, 0, n, s);
+}
+
+hipError_t launch_copy_lower_rows(const double* A, int64_t lda, double* L, int64_t ldl, int64_t c0,
+                                  int64_t c1, int64_t rb, int64_t re, hipStream_t s) {
+  if (c1 <= c0 || re <= rb) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_lower, dim3((unsigned)(c1 - c0)), dim3(256), 0, s, A, lda, L, ldl, c0,
+                     rb, re);
   return hipGetLastError();
 }
 

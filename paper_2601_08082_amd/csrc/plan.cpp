@@ -524,6 +524,10 @@ struct Builder {
     int p = node_prec(id, depth);
     int64_t m1 = split_rule(m, t.split_align), m2 = m - m1;
     potrf(i0, m1, depth + 1);
+    if (depth == 0) {
+      P.split1 = m1;
+      P.first_outer = (int)P.launches.size();
+    }
     trsm(i0 + m1, m2, i0, m1, p);
     syrk(i0 + m1, m2, i0, m1, p);
     potrf(i0 + m1, m2, depth + 1);

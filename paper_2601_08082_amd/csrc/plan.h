@@ -45,6 +45,8 @@ struct Plan {
   size_t ws_bytes = 0;     // quantized-operand workspace needed
   int64_t parts = 0;       // maxabs partial slots needed
   int ninv = 0;            // leaf-inverse slots (kInvLd x kInvLd doubles each)
+  int64_t split1 = 0;      // order of the top-level A11 (0: the root is a leaf)
+  int first_outer = -1;    // first launch that touches rows >= split1
   PlanStats stats;
   // device copies of the descriptor arrays
   MaxabsJob* d_maxabs = nullptr;
