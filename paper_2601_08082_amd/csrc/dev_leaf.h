@@ -431,36 +431,47 @@ __device__ inline void trinv_body(const double* __restrict__ Lm, int64_t ldl, in
 // Rows [r0 + 16 rblk, +16) of B <- B L^{-T} = B Y^T with Y = L^{-1} (k <=
 // 16 NCB, column-major, ld ldy, lower): X(i, j) = sum_{l <= j} B(i, l) Y(j, l),
 // FP64 MFMA.  The 16-column blocks are dealt to the waves in mirrored pairs
-// (w, NCB - 1 - w, ...) for balance; every wave reads the whole row block of
-// B before any wave writes (in place).
+// (w, NCB - 1 - w) for balance; the row block of B is read into LDS before
+// any wave writes it back (in place).  bs: 16 NCB x 17 doubles of LDS.
 template <int NCB>
 __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64_t r0, int64_t m,
                                      int64_t c0, int k, const double* __restrict__ Y, int ldy,
-                                     int rblk) {
-  constexpr int PER = NCB / 4;                 // column blocks per wave
+                                     int rblk, double* bs) {
+  // NCB / 2 waves (blockDim.x = 32 NCB), two column blocks each, mirrored
+  // (w, NCB - 1 - w) so every wave multiplies NCB + 1 chunks; with NCB = 16
+  // two waves share a SIMD and each keeps its own loads in flight
+  constexpr int PER = 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t rb = r0 + (int64_t)rblk * IB;
   const int rows = (int)min((int64_t)IB, r0 + m - rb);
   const int nb = (k + IB - 1) / IB;
   double* B = Lm + rb + c0 * ldl;
-  int cbs[PER];
-#pragma unroll
-  for (int h = 0; h < PER; h++) cbs[h] = (h & 1) ? 4 * (h + 1) - 1 - wave : 4 * h + wave;
+  const int cbs[PER] = {wave, NCB - 1 - wave};
   // Every load is unconditional from a clamped address and masked on its bits
   // (a select on a loaded value becomes a branch that waits for the load).
   auto keep = [](double v, bool ok) {
     return __longlong_as_double(__double_as_longlong(v) & (ok ? -1ll : 0ll));
   };
-  // A fragments: a[lb][q] = B(lane%16, 16 lb + 4 q + lane/16)
-  double a[NCB][4];
-  const int ri = min(lane & 15, rows - 1);
+  // The row block of B in LDS, bs[col * 17 + row] (zero-padded), loaded by
+  // all threads with every load in flight; A fragments come from there.
+  constexpr int NT = 32 * NCB, PERT = 16 * 16 * NCB / NT;   // 8 elements per thread
+  {
+    double v[PERT];
 #pragma unroll
-  for (int lb = 0; lb < NCB; lb++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int col = 16 * lb + 4 * q + (lane >> 4);
-      a[lb][q] = keep(B[ri + (int64_t)min(col, k - 1) * ldl], col < k && (lane & 15) < rows);
+    for (int u = 0; u < PERT; u++) {
+      const int idx = tid + NT * u, row = idx & 15, col = idx >> 4;
+      v[u] = keep(B[min(row, rows - 1) + (int64_t)min(col, k - 1) * ldl], row < rows && col < k);
     }
+#pragma unroll
+    for (int u = 0; u < PERT; u++) {
+      const int idx = tid + NT * u;
+      bs[(idx >> 4) * 17 + (idx & 15)] = v[u];
+    }
+  }
+  __syncthreads();   // also: every read of B is complete before any wave writes B
+  auto afrag = [&](int lb, int q) {
+    return bs[(16 * lb + 4 * q + (lane >> 4)) * 17 + (lane & 15)];
+  };
   // B-operand fragments of k-chunk lb for this wave's column blocks:
   // (kk, col) = Y(16 cb + col, 16 lb + 4 q + kk); the next chunk's are in
   // flight while this chunk's products run
@@ -488,13 +499,12 @@ __device__ inline void trsm_inv_rows(double* __restrict__ Lm, int64_t ldl, int64
       if (lb <= cbs[h] && cbs[h] < nb)   // wave-uniform
 #pragma unroll
         for (int q = 0; q < 4; q++)
-          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lb][q], ya[h][q], acc[h], 0, 0, 0);
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag(lb, q), ya[h][q], acc[h], 0, 0, 0);
 #pragma unroll
     for (int h = 0; h < PER; h++)
 #pragma unroll
       for (int q = 0; q < 4; q++) ya[h][q] = yn[h][q];
   }
-  __syncthreads();   // every wave has consumed its reads of B
 #pragma unroll
   for (int h = 0; h < PER; h++) {
     const int cb = cbs[h];
@@ -565,38 +575,6 @@ __device__ inline void inv_join_tile(const double* __restrict__ L21, int64_t ldl
       const int row = 16 * ti + (lane >> 4) + 4 * rr, col = 16 * tc + (lane & 15);
       if (row < m2 && col < m1) Y21[row + (int64_t)col * ldy] = -acc[rr];
     }
-  }
-}
-
-// C(M x N) = alpha A(M x K) B(K x N), all column-major FP64, M, N, K <= 128:
-// one wave per 16 x 16 output tile (blockIdx.x = tile), FP64 MFMA.  Used to
-// join two leaf inverses into the inverse of their parent block.
-__device__ inline void small_gemm_tile(double* __restrict__ C, int ldc, const double* __restrict__ A,
-                                       int64_t lda, const double* __restrict__ Bm, int ldb, int M,
-                                       int N, int K, double alpha) {
-  const int lane = threadIdx.x & 63;
-  const int tiles_m = (M + 15) / 16;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int i = 16 * tm + (lane & 15), j = 16 * tn + (lane & 15);
-  // all fragments in flight first (K <= 128: 32 of each), then the MFMA chain
-  double av[KL / 4], bv[KL / 4];
-  const int ic = min(i, M - 1), jc = min(j, N - 1);
-#pragma unroll
-  for (int q = 0; q < KL / 4; q++) {
-    const int kk = 4 * q + (lane >> 4), kc = min(kk, K - 1);
-    const double a = A[ic + (int64_t)kc * lda];
-    const double b = Bm[kc + (int64_t)jc * ldb];
-    av[q] = (i < M && kk < K) ? a : 0.0;
-    bv[q] = (j < N && kk < K) ? b : 0.0;
-  }
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < KL / 4; q++)
-    if (4 * q < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
-#pragma unroll
-  for (int r = 0; r < 4; r++) {
-    const int row = 16 * tm + (lane >> 4) + 4 * r, col = 16 * tn + (lane & 15);
-    if (row < M && col < N) C[row + (int64_t)col * ldc] = alpha * acc[r];
   }
 }
 

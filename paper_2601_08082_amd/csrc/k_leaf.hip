@@ -20,10 +20,10 @@
 // FP64 leaves can instead be solved through their inverse: k_potrf_inv (or
 // k_trinv on its own) forms Y = L^{-1} once per leaf (block substitution,
 // FP64 MFMA for the off-diagonal blocks; k_potrf_inv right after the
-// factorization, from its LDS copy) and k_trsm_inv computes B <- B Y^T as an FP64 MFMA
-// product, 16 rows per workgroup, with no dependency chain along the
-// columns.  Same values up to rounding; the substitution kernel remains the
-// bit-exact reference mode.
+// factorization, from its LDS copy) and k_trsm_inv (k_trsm_inv.hip) computes
+// B <- B Y^T as an FP64 MFMA product, 16 rows per workgroup, with no
+// dependency chain along the columns.  Same values up to rounding; the
+// substitution kernel remains the bit-exact reference mode.
 #include "dev_leaf.h"
 
 namespace mpc {
@@ -61,13 +61,6 @@ __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Lm, in
   trinv_body(Lm, ldl, i0, m, Y, ldy, pool);
 }
 
-template <int NCB>
-__global__ __launch_bounds__(256) void k_trsm_inv(double* __restrict__ Lm, int64_t ldl, int64_t r0,
-                                                  int64_t m, int64_t c0, int k,
-                                                  const double* __restrict__ Y, int ldy) {
-  trsm_inv_rows<NCB>(Lm, ldl, r0, m, c0, k, Y, ldy, blockIdx.x);
-}
-
 __global__ __launch_bounds__(256) void k_inv_join(const double* __restrict__ L21, int64_t ldl,
                                                   const double* __restrict__ Y1,
                                                   const double* __restrict__ Y2,
@@ -75,13 +68,6 @@ __global__ __launch_bounds__(256) void k_inv_join(const double* __restrict__ L21
                                                   int m2) {
   __shared__ double t[KL * 17];
   inv_join_tile(L21, ldl, Y1, Y2, Y21, ldy, m1, m2, blockIdx.x, blockIdx.y, t);
-}
-
-__global__ __launch_bounds__(64) void k_small_gemm(double* __restrict__ C, int ldc,
-                                                   const double* __restrict__ A, int64_t lda,
-                                                   const double* __restrict__ B, int ldb, int M,
-                                                   int N, int K, double alpha) {
-  small_gemm_tile(C, ldc, A, lda, B, ldb, M, N, K, alpha);
 }
 
 // Inverses of the 64 x 64 diagonal blocks of L (the last one ragged), one
@@ -113,18 +99,6 @@ hipError_t launch_trinv(const double* Lm, int64_t ldl, int64_t i0, int m, double
   if (m <= 0) return hipSuccess;
   if (m > KL || ldy < KL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_trinv, dim3(1), dim3(256), 0, s, Lm, ldl, i0, m, Y, ldy);
-  return hipGetLastError();
-}
-
-hipError_t launch_trsm_inv(double* Lm, int64_t ldl, int64_t r0, int64_t m, int64_t c0, int k,
-                           const double* Y, int ldy, hipStream_t s) {
-  if (m <= 0 || k <= 0) return hipSuccess;
-  if (k > 2 * KL || ldy < k) return hipErrorInvalidValue;
-  const dim3 g((unsigned)((m + 15) / 16));
-  if (k <= KL)
-    hipLaunchKernelGGL(k_trsm_inv<8>, g, dim3(256), 0, s, Lm, ldl, r0, m, c0, k, Y, ldy);
-  else
-    hipLaunchKernelGGL(k_trsm_inv<16>, g, dim3(256), 0, s, Lm, ldl, r0, m, c0, k, Y, ldy);
   return hipGetLastError();
 }
 
