@@ -6,7 +6,8 @@
 // with FP32 accumulation for FP16 / E4M3 / FP32 operands and FP64 for FP64
 // (Section 3.3 layering; Section 3.4 dequantization by the block scales).
 // One launch handles a list of independent problems; every workgroup owns one
-// output tile (64 or 128 square) of one problem.  The bodies live in
+// output tile (64 or 128 square; 32 for small FP32 / FP64 groups) of one
+// problem.  The bodies live in
 // dev_gemm.h.
 //
 // Output orientation: the MFMA computes D = Y X^T so that the lane index runs
@@ -83,6 +84,12 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
     launch_gemm_bm<64>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
   } else if (tile == 128) {
     launch_gemm_bm<128>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
+  } else if (tile == 32 && prec == F32) {   // small FP32 / FP64 groups: more workgroups
+    hipLaunchKernelGGL((k_gemm_f32q<32>), g, b, 0, s, Lm, ldl, (const float*)ws, probs, nprobs,
+                       part, prec, scale_mode, st);
+  } else if (tile == 32 && prec == F64) {
+    hipLaunchKernelGGL((k_gemm_d<double, 32>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
+                       scale_mode, st);
   } else {
     return hipErrorInvalidValue;
   }
