@@ -383,9 +383,9 @@ struct Builder {
       } else {
         // 128 x 128 tiles unless that leaves most of the 256 CUs idle (256 x
         // 256 tiles measured slower: one wave per SIMD, fewer loads in flight);
-        // FP32 / FP64 groups too small for 128 64-tiles take 32-tiles
+        // FP32 / FP64 groups with fewer than 256 64-tiles take 32-tiles
         L.tile = tiles_of(128) >= 256 ? 128 : 64;
-        if (L.tile == 64 && (prec == F32 || prec == F64) && tiles_of(64) < 128) L.tile = 32;
+        if (L.tile == 64 && (prec == F32 || prec == F64) && tiles_of(64) < 256) L.tile = 32;
       }
       int tiles = 0;
       for (auto& g : gp) {
