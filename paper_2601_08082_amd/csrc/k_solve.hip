@@ -253,43 +253,44 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
     }
     return;
   }
-  // v = b - (the folded sums); x = Y v (forward) or Y^T v (transposed)
+  // v = b - (the folded sums); x = Y v (forward) or Y^T v (transposed):
+  // wave g forms rows 16 g .. 16 g + 15, lane quarter qq the terms
+  // q = 16 qq .. 16 qq + 15 of each, the quarters added by two lane swaps
+  // (fixed order), and the first quarter publishes; no barrier after v
   if (tid < 64) {
 #pragma unroll
     for (int c = 0; c < NR; c++)
       xs[0][r][c] = bval[c] - ((acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]));
   }
   __syncthreads();
+  {
+    const int row = 16 * g + (r & 15), qq = r >> 4;
 #pragma unroll
-  for (int c = 0; c < NR; c++) part[c] = 0.0;
-  if (!trans) {
-    for (int q = g; q < NB; q += 4) {
-      const double y = dg[q][r];
+    for (int c = 0; c < NR; c++) part[c] = 0.0;
 #pragma unroll
-      for (int c = 0; c < NR; c++) part[c] += y * xs[0][q][c];
-    }
-  } else {
-    for (int q = g; q < NB; q += 4) {
-      const double y = dg[r][q];
+    for (int j = 0; j < 16; j++) {
+      const int q = 16 * qq + j;
+      const double y = trans ? dg[row][q] : dg[q][row];
 #pragma unroll
       for (int c = 0; c < NR; c++) part[c] += y * xs[0][q][c];
     }
-  }
-  __syncthreads();   // every wave has read acc
 #pragma unroll
-  for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
-  __syncthreads();
-  if (tid < 64) {
+    for (int c = 0; c < NR; c++) {
+      part[c] += __shfl_xor(part[c], 16, 64);
+      part[c] += __shfl_xor(part[c], 32, 64);
+    }
+    if (qq == 0) {
 #pragma unroll
-    for (int c = 0; c < NR; c++)
-      if (c < nrhs && r < nj) {
-        const double v = (acc[0][r][c] + acc[1][r][c]) + (acc[2][r][c] + acc[3][r][c]);
-        X[(j0 + r) + (int64_t)c * ldx] = v;
-        // the published copy, coherent across the dies without a fence
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + r) + (int64_t)c * n),
-                           (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
+      for (int c = 0; c < NR; c++)
+        if (c < nrhs && row < nj) {
+          const double v = part[c];
+          X[(j0 + row) + (int64_t)c * ldx] = v;
+          // the published copy, coherent across the dies without a fence
+          __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + row) + (int64_t)c * n),
+                             (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
   }
 }
 
