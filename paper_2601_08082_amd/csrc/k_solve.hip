@@ -235,7 +235,8 @@ __global__ __launch_bounds__(256) void k_trsv2(int trans, const double* __restri
     }
     if (sk < k_end) step(sk, la, lb);
   }
-  __syncthreads();
+  // acc is written only here; the barrier after it also orders every read of
+  // xs in the last step before v overwrites xs[0]
 #pragma unroll
   for (int c = 0; c < NR; c++) acc[g][r][c] = part[c];
   __syncthreads();
