@@ -970,8 +970,7 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
         int32_t t0 = (int32_t)tasks.size();
         for (const Launch& L : P.launches) {
           if (L.kind == Launch::TRINV || L.kind == Launch::INVJOIN ||
-              (L.kind == Launch::CAST && L.a0 == 1) || (L.kind == Launch::TRSM && L.first >= 0) ||
-              (L.kind == Launch::POTRF && L.a2 == 1)) {
+              (L.kind == Launch::TRSM && L.first >= 0) || (L.kind == Launch::POTRF && L.a2 == 1)) {
             free_batch(c);
             return MPCHOL_HIP_ERROR;   // workgroup-level plans never use leaf inverses
           }

@@ -25,6 +25,7 @@ static_assert(kPool >= potrf_leaf_lds_bytes<double>(), "pool");
 static_assert(kPool >= gemm_q_lds_bytes<_Float16, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<double, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<float, 128>(), "pool");
+static_assert(kPool >= cast_lds_bytes<_Float16>(), "pool");
 
 __device__ inline int find_job_max(const MaxabsJob* j, int nj, int w) {
   int lo = 0, hi = nj - 1;
@@ -337,6 +338,13 @@ __device__ void run_task(const BatchTask& T, const BatchProgram& prog, double* L
     }
     case BatchTask::CAST: {
       const CastJob* jobs = prog.casts + T.first;
+      if (T.a0 == 1) {
+        // single pass (FP16, scale_mode 0): scale-1 copies with one max-abs
+        // partial per work unit; the GEMM tasks take the block scales from them
+        cast_max_tiles<_Float16>(L, ldl, jobs, T.count, 0, 1, T.total, part, T.prec,
+                                 reinterpret_cast<_Float16*>(ws), pool);
+        break;
+      }
       for (int w = 0; w < T.total; w++) {
         const CastJob& jb = jobs[find_job_cast(jobs, T.count, w)];
         if (T.prec == F16)

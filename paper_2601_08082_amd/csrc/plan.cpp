@@ -165,7 +165,7 @@ struct Builder {
     // FP16 with scale_mode 0 (and FP32): one pass casts at scale 1 and
     // records the max-abs
     const bool single_pass =
-        ((prec == F16 && t.scale_mode == 0) || prec == F32) && !single_wg;
+        (prec == F16 && t.scale_mode == 0) || (prec == F32 && !single_wg);
     if (single_pass) with_parts = false;
     // Single pass: operands of the group with the same columns whose rows
     // overlap or touch share one scale-1 copy of the union of their rows (a
