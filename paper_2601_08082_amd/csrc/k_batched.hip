@@ -82,30 +82,68 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
     double part[NR];
 #pragma unroll
     for (int c = 0; c < NR; c++) part[c] = 0.0;
-    for (int u = 0; u < s; u++) {
+    // Blocks u < s: thread (r, g) holds L(j0 + r, k0 + g + 4 w) (forward) or
+    // L(k0 + r, j0 + g + 4 w) (transposed, regrouped through blk) in
+    // registers, addresses clamped and values masked at use, with the next
+    // block's loads in flight during this one.
+    auto keep = [](double v, bool ok) {
+      return __longlong_as_double(__double_as_longlong(v) & (ok ? -1ll : 0ll));
+    };
+    auto load_blk = [&](int u, double (&v)[16]) {
       const int K = trans ? nb - 1 - u : u;
       const int k0 = K * 64, nk = min(64, n - k0);
-      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < 16; w++) {
+        const int q = g + 4 * w;
+        const int64_t row = trans ? k0 + min(r, nk - 1) : j0 + min(r, nj - 1);
+        const int64_t col = trans ? j0 + min(q, nj - 1) : k0 + min(q, nk - 1);
+        v[w] = L[row + col * ldl];
+      }
+    };
+    auto step = [&](int u, double (&cur)[16], double (&nxt)[16]) {
+      load_blk(min(u + 1, s - 1), nxt);   // past the end: a block nobody uses
+      const int K = trans ? nb - 1 - u : u;
+      const int k0 = K * 64, nk = min(64, n - k0);
+      __syncthreads();   // the previous block's readers of xs and blk are done
       for (int idx = tid; idx < 64 * NR; idx += 256) {
         const int q = idx & 63, c = idx >> 6;
         xs[q * NR + c] = (q < nk && c < nrhs) ? X[(k0 + q) + (int64_t)c * n] : 0.0;
       }
-      if (trans) stage_block(blk, L, ldl, k0, j0, nk, nj);   // L(K, J)
+      if (trans) {
+#pragma unroll
+        for (int w = 0; w < 16; w++) {
+          const int q = g + 4 * w;
+          blk[q][r] = keep(cur[w], r < nk && q < nj);   // blk[q][i] = L(k0 + i, j0 + q)
+        }
+      }
       __syncthreads();
       if (!trans) {
-        if (r < nj)
-          for (int q = g; q < nk; q += 4) {
-            const double l = L[(j0 + r) + (int64_t)(k0 + q) * ldl];
 #pragma unroll
-            for (int c = 0; c < NR; c++) part[c] += l * xs[q * NR + c];
-          }
+        for (int w = 0; w < 16; w++) {
+          const int q = g + 4 * w;
+          const double l = keep(cur[w], r < nj && q < nk);
+#pragma unroll
+          for (int c = 0; c < NR; c++) part[c] += l * xs[q * NR + c];
+        }
       } else {
-        for (int i = g; i < nk; i += 4) {
+#pragma unroll
+        for (int w = 0; w < 16; w++) {
+          const int i = g + 4 * w;
           const double l = blk[r][i];
 #pragma unroll
           for (int c = 0; c < NR; c++) part[c] += l * xs[i * NR + c];
         }
       }
+    };
+    if (s > 0) {
+      double la[16], lb[16];
+      load_blk(0, la);
+      int u = 0;
+      for (; u + 1 < s; u += 2) {
+        step(u, la, lb);
+        step(u + 1, lb, la);
+      }
+      if (u < s) step(u, la, lb);
     }
     __syncthreads();
 #pragma unroll
