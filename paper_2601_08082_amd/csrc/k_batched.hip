@@ -206,14 +206,27 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
     double colsum[NR];                   // rows I (lane q = tid, wave 0), from the blocks below
 #pragma unroll
     for (int c = 0; c < NR; c++) colsum[c] = 0.0;
-    for (int J = I; J < nb; J++) {
+    // block A(J, I) of the next J loaded into registers while this one is
+    // used (addresses clamped, values masked when staged)
+    auto keep = [](double v, bool ok) {
+      return __longlong_as_double(__double_as_longlong(v) & (ok ? -1ll : 0ll));
+    };
+    auto load_a = [&](int J, double (&v)[16]) {
+      const int j0 = J * 64, nj = min(64, n - j0);
+#pragma unroll
+      for (int w = 0; w < 16; w++) {
+        const int idx = tid + 256 * w, rr = idx & 63, q = idx >> 6;
+        v[w] = A[(j0 + min(rr, nj - 1)) + (int64_t)(i0 + min(q, ni - 1)) * lda];
+      }
+    };
+    auto body = [&](int J, double (&cur)[16], double (&nxt)[16]) {
+      load_a(min(J + 1, nb - 1), nxt);   // past the end: a block nobody uses
       const int j0 = J * 64, nj = min(64, n - j0);
       __syncthreads();
-      for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int rr = idx & 63, q = idx >> 6;
-        double v = 0.0;
-        if (rr < nj && q < ni && (J > I || rr >= q)) v = A[(j0 + rr) + (int64_t)(i0 + q) * lda];
-        blk[q][rr] = v;
+#pragma unroll
+      for (int w = 0; w < 16; w++) {
+        const int idx = tid + 256 * w, rr = idx & 63, q = idx >> 6;
+        blk[q][rr] = keep(cur[w], rr < nj && q < ni && (J > I || rr >= q));
       }
       for (int idx = tid; idx < 64 * NR; idx += 256) {
         const int q = idx & 63, c = idx >> 6;
@@ -244,6 +257,16 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
           for (int c = 0; c < NR; c++) colsum[c] += a * xj[rr * NR + c];
         }
       }
+    };
+    {
+      double va[16], vb[16];
+      load_a(I, va);
+      int J = I;
+      for (; J + 1 < nb; J += 2) {
+        body(J, va, vb);
+        body(J + 1, vb, va);
+      }
+      if (J < nb) body(J, va, vb);
     }
     __syncthreads();
     if (tid >= 64 && tid < 128) {
