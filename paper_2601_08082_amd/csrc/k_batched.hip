@@ -100,14 +100,28 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
         v[w] = L[row + col * ldl];
       }
     };
-    auto step = [&](int u, double (&cur)[16], double (&nxt)[16]) {
+    // x of block u (solved earlier), XPT values per thread, likewise one block ahead
+    constexpr int XPT = (64 * NR + 255) / 256;
+    auto load_x = [&](int u, double (&v)[XPT]) {
+      const int K = trans ? nb - 1 - u : u;
+      const int k0 = K * 64, nk = min(64, n - k0);
+#pragma unroll
+      for (int t = 0; t < XPT; t++) {
+        const int idx = tid + 256 * t, q = idx & 63, c = min(idx >> 6, NR - 1);
+        v[t] = X[(k0 + min(q, nk - 1)) + (int64_t)min(c, nrhs - 1) * n];
+      }
+    };
+    auto step = [&](int u, double (&cur)[16], double (&nxt)[16], double (&xc)[XPT],
+                    double (&xn)[XPT]) {
       load_blk(min(u + 1, s - 1), nxt);   // past the end: a block nobody uses
+      load_x(min(u + 1, s - 1), xn);
       const int K = trans ? nb - 1 - u : u;
       const int k0 = K * 64, nk = min(64, n - k0);
       __syncthreads();   // the previous block's readers of xs and blk are done
-      for (int idx = tid; idx < 64 * NR; idx += 256) {
-        const int q = idx & 63, c = idx >> 6;
-        xs[q * NR + c] = (q < nk && c < nrhs) ? X[(k0 + q) + (int64_t)c * n] : 0.0;
+#pragma unroll
+      for (int t = 0; t < XPT; t++) {
+        const int idx = tid + 256 * t, q = idx & 63, c = idx >> 6;
+        if (idx < 64 * NR) xs[q * NR + c] = keep(xc[t], q < nk && c < nrhs);
       }
       if (trans) {
 #pragma unroll
@@ -136,14 +150,15 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
       }
     };
     if (s > 0) {
-      double la[16], lb[16];
+      double la[16], lb[16], xa[XPT], xb[XPT];
       load_blk(0, la);
+      load_x(0, xa);
       int u = 0;
       for (; u + 1 < s; u += 2) {
-        step(u, la, lb);
-        step(u + 1, lb, la);
+        step(u, la, lb, xa, xb);
+        step(u + 1, lb, la, xb, xa);
       }
-      if (u < s) step(u, la, lb);
+      if (u < s) step(u, la, lb, xa, xb);
     }
     __syncthreads();
 #pragma unroll
