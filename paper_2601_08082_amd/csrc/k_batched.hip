@@ -55,9 +55,18 @@ __device__ inline double wg_bcast(double v, int src) {
 // rows < nr, cols < nc); lanes run along rows (coalesced).
 __device__ inline void stage_block(double (*blk)[65], const double* __restrict__ M, int64_t ld,
                                    int r0, int c0, int nr, int nc) {
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    const int i = idx & 63, q = idx >> 6;
-    blk[q][i] = (i < nr && q < nc) ? M[(r0 + i) + (int64_t)(c0 + q) * ld] : 0.0;
+  // all 16 loads of a thread in flight (addresses clamped), masked on their
+  // bits when stored: a select on a loaded value waits for each load in turn
+  double v[16];
+#pragma unroll
+  for (int w = 0; w < 16; w++) {
+    const int idx = threadIdx.x + 256 * w, i = idx & 63, q = idx >> 6;
+    v[w] = M[(r0 + min(i, nr - 1)) + (int64_t)(c0 + min(q, nc - 1)) * ld];
+  }
+#pragma unroll
+  for (int w = 0; w < 16; w++) {
+    const int idx = threadIdx.x + 256 * w, i = idx & 63, q = idx >> 6;
+    blk[q][i] = __longlong_as_double(__double_as_longlong(v[w]) & ((i < nr && q < nc) ? -1ll : 0ll));
   }
 }
 
