@@ -243,18 +243,38 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
         v[w] = A[(j0 + min(rr, nj - 1)) + (int64_t)(i0 + min(q, ni - 1)) * lda];
       }
     };
-    auto body = [&](int J, double (&cur)[16], double (&nxt)[16]) {
-      load_a(min(J + 1, nb - 1), nxt);   // past the end: a block nobody uses
+    // x of block J, likewise one block ahead
+    constexpr int XPT = (64 * NR + 255) / 256;
+    auto load_x = [&](int J, double (&v)[XPT]) {
       const int j0 = J * 64, nj = min(64, n - j0);
+#pragma unroll
+      for (int t = 0; t < XPT; t++) {
+        const int idx = tid + 256 * t, q = idx & 63, c = min(idx >> 6, NR - 1);
+        v[t] = X[(j0 + min(q, nj - 1)) + (int64_t)min(c, nrhs - 1) * n];
+      }
+    };
+    auto body = [&](int J, double (&cur)[16], double (&nxt)[16], double (&xc)[XPT],
+                    double (&xn)[XPT]) {
+      load_a(min(J + 1, nb - 1), nxt);   // past the end: a block nobody uses
+      load_x(min(J + 1, nb - 1), xn);
+      const int j0 = J * 64, nj = min(64, n - j0);
+      // the running sums of rows J (wave 0 adds to them below), read early
+      double rs[NR];
+      if (tid < 64) {
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+          rs[c] = R[(j0 + min(tid, nj - 1)) + (int64_t)min(c, nrhs - 1) * n];
+      }
       __syncthreads();
 #pragma unroll
       for (int w = 0; w < 16; w++) {
         const int idx = tid + 256 * w, rr = idx & 63, q = idx >> 6;
         blk[q][rr] = keep(cur[w], rr < nj && q < ni && (J > I || rr >= q));
       }
-      for (int idx = tid; idx < 64 * NR; idx += 256) {
-        const int q = idx & 63, c = idx >> 6;
-        xj[q * NR + c] = (q < nj && c < nrhs) ? X[(j0 + q) + (int64_t)c * n] : 0.0;
+#pragma unroll
+      for (int t = 0; t < XPT; t++) {
+        const int idx = tid + 256 * t, q = idx & 63, c = idx >> 6;
+        if (idx < 64 * NR) xj[q * NR + c] = keep(xc[t], q < nj && c < nrhs);
       }
       __syncthreads();
       if (tid < 64) {
@@ -271,7 +291,7 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
         if (rr < nj)
 #pragma unroll
           for (int c = 0; c < NR; c++)
-            if (c < nrhs) R[(j0 + rr) + (int64_t)c * n] += y[c];
+            if (c < nrhs) R[(j0 + rr) + (int64_t)c * n] = rs[c] + y[c];
       } else if (tid < 128) {
         // rows of I: sum over r of A(j0 + r, i0 + q) x_J(r), strictly below the diagonal
         const int q = tid - 64;
@@ -283,14 +303,15 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
       }
     };
     {
-      double va[16], vb[16];
+      double va[16], vb[16], xa[XPT], xb[XPT];
       load_a(I, va);
+      load_x(I, xa);
       int J = I;
       for (; J + 1 < nb; J += 2) {
-        body(J, va, vb);
-        body(J + 1, vb, va);
+        body(J, va, vb, xa, xb);
+        body(J + 1, vb, va, xb, xa);
       }
-      if (J < nb) body(J, va, vb);
+      if (J < nb) body(J, va, vb, xa, xb);
     }
     __syncthreads();
     if (tid >= 64 && tid < 128) {
