@@ -214,7 +214,8 @@ constexpr int trsm_leaf_lds_bytes() {
 // Rows [r0 + 64 rblk, r0 + 64 rblk + 64) of B <- B L^{-T}.
 template <typename T>
 __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int64_t r0,
-                                      int64_t m, int64_t c0, int k, int rblk, char* lds) {
+                                      int64_t m, int64_t c0, int k, int rblk, char* lds,
+                                      bool with_l = true) {
   constexpr int LDB = KL + 1;
   T* l = reinterpret_cast<T*>(lds);  // packed lower L
   T* b = l + KL * (KL + 1) / 2;      // b[r * LDB + c]
@@ -228,13 +229,18 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
   double* B = Lm + rb + c0 * ldl;
   auto loff = [kp](int i, int j) { return j * kp - (j * (j - 1)) / 2 + (i - j); };  // i >= j
   {
-    // all loads of a thread in flight before the first LDS store
+    // all loads of a thread in flight before the first LDS store; with_l
+    // false: L and its reciprocals are still in LDS from the previous row
+    // block of the same strip (the batched executor walks a strip in one
+    // workgroup)
     double v[KL * KL / 256], w[64 * KL / 256];
+    if (with_l) {
 #pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      v[r] = L[min(i, k - 1) + (int64_t)min(j, k - 1) * ldl];
+      for (int r = 0; r < KL * KL / 256; r++) {
+        const int idx = tid + 256 * r;
+        const int i = idx % KL, j = idx / KL;
+        v[r] = L[min(i, k - 1) + (int64_t)min(j, k - 1) * ldl];
+      }
     }
 #pragma unroll
     for (int r = 0; r < 64 * KL / 256; r++) {
@@ -242,11 +248,13 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
       const int i = idx & 63, j = idx >> 6;
       w[r] = B[min(i, rows - 1) + (int64_t)min(j, k - 1) * ldl];
     }
+    if (with_l) {
 #pragma unroll
-    for (int r = 0; r < KL * KL / 256; r++) {
-      const int idx = tid + 256 * r;
-      const int i = idx % KL, j = idx / KL;
-      if (i < kp && j < kp && i >= j) l[loff(i, j)] = (i < k && j < k) ? (T)v[r] : (T)(i == j ? 1 : 0);
+      for (int r = 0; r < KL * KL / 256; r++) {
+        const int idx = tid + 256 * r;
+        const int i = idx % KL, j = idx / KL;
+        if (i < kp && j < kp && i >= j) l[loff(i, j)] = (i < k && j < k) ? (T)v[r] : (T)(i == j ? 1 : 0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 64 * KL / 256; r++) {
@@ -256,8 +264,10 @@ __device__ inline void trsm_leaf_rows(double* __restrict__ Lm, int64_t ldl, int6
     }
   }
   __syncthreads();
-  if (tid < kp) inv[tid] = (T)1 / l[loff(tid, tid)];
-  __syncthreads();
+  if (with_l) {
+    if (tid < kp) inv[tid] = (T)1 / l[loff(tid, tid)];
+    __syncthreads();
+  }
   for (int p = 0; p < kp; p += PW) {
     if (wave == 0) {
       // substitution inside the panel, lane = row, in registers

@@ -406,7 +406,7 @@ __device__ __noinline__ void nb_potrf(double* L, int64_t ldl, int64_t i0, int m,
 template <typename T>
 __device__ __noinline__ void nb_trsm(double* L, int64_t ldl, int64_t r0, int64_t m, int64_t c0,
                                      int k, int rb, char* pool) {
-  trsm_leaf_rows<T>(L, ldl, r0, m, c0, k, rb, pool);
+  trsm_leaf_rows<T>(L, ldl, r0, m, c0, k, rb, pool, rb == 0);   // the strip's L loaded once
 }
 template <typename Q>
 __device__ __noinline__ void nb_cast(const double* L, int64_t ldl, const CastJob* jb, int t,
