@@ -121,9 +121,10 @@ __device__ __attribute__((always_inline)) inline void potrf_leaf_body(
     // panel's diagonal block (rows p..p+15) in every wave, lanes 16..63 of
     // wave w hold rows p + 16 + 48 w + (lane - 16).  Each wave repeats the
     // diagonal block's elimination (bitwise the same in all waves) so that
-    // no column has to cross waves; the per-column chain is one broadcast, a
-    // square root, one reciprocal and a Markstein quotient.  Entries above
-    // the diagonal start at zero and are never read back or stored.
+    // no column has to cross waves; the per-column chain is one broadcast,
+    // the square root and reciprocal of sqrt_rcp, and a Markstein quotient.
+    // Entries above the diagonal start at zero and are never read back or
+    // stored.
     const int lrow = lane < PW ? p + lane : p + PW + 48 * wave + (lane - PW);
     if (wave == 0 || p + PW + 48 * wave < mp) {
       T x[PW];
