@@ -174,14 +174,21 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
     for (int c = 0; c < NR; c++) acc[(g * 64 + r) * NR + c] = part[c];
     stage_block(dg, L, ldl, j0, j0, nj, nj);
     __syncthreads();
-    if (tid < 64) {
-      const int i = tid;
-      double v[NR];
+    // the diagonal block: wave g substitutes right-hand sides g, g + 4, ...
+    // (independent chains), one lane per row
+    constexpr int CPW = NR >= 4 ? NR / 4 : 1;   // columns per wave
+    if (g < NR && g < nrhs) {
+      const int i = r;
+      double v[CPW];
 #pragma unroll
-      for (int c = 0; c < NR; c++) {
+      for (int h = 0; h < CPW; h++) {
+        const int c = g + 4 * h;
         const double b = (c < nrhs && i < nj) ? X[(j0 + i) + (int64_t)c * n] : 0.0;
-        v[c] = b - ((acc[(0 * 64 + i) * NR + c] + acc[(1 * 64 + i) * NR + c]) +
-                    (acc[(2 * 64 + i) * NR + c] + acc[(3 * 64 + i) * NR + c]));
+        v[h] = c < NR ? b - ((acc[(0 * 64 + i) * NR + min(c, NR - 1)] +
+                              acc[(1 * 64 + i) * NR + min(c, NR - 1)]) +
+                             (acc[(2 * 64 + i) * NR + min(c, NR - 1)] +
+                              acc[(3 * 64 + i) * NR + min(c, NR - 1)]))
+                      : 0.0;
       }
       const double inv = i < nj ? 1.0 / dg[i][i] : 0.0;
       for (int jj = 0; jj < nj; jj++) {
@@ -190,15 +197,17 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
         const double ij = wg_bcast(inv, j);
         const bool below = trans ? (i < j) : (i > j);
 #pragma unroll
-        for (int c = 0; c < NR; c++) {
-          const double xj = wg_bcast(v[c], j) * ij;
-          const double upd = v[c] - lij * xj;
-          v[c] = i == j ? xj : (below ? upd : v[c]);
+        for (int h = 0; h < CPW; h++) {
+          const double xj = wg_bcast(v[h], j) * ij;
+          const double upd = v[h] - lij * xj;
+          v[h] = i == j ? xj : (below ? upd : v[h]);
         }
       }
 #pragma unroll
-      for (int c = 0; c < NR; c++)
-        if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * n] = v[c];
+      for (int h = 0; h < CPW; h++) {
+        const int c = g + 4 * h;
+        if (c < nrhs && i < nj) X[(j0 + i) + (int64_t)c * n] = v[h];
+      }
     }
     __syncthreads();
   }
