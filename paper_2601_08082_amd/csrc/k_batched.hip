@@ -217,7 +217,9 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
 // one workgroup.  Each stored 64 x 64 block A(J, I), J >= I, is staged
 // through LDS and used twice: A(J, I) x_I into rows J (lane = row) and
 // A(J, I)^T x_J into rows I (lane = column); R holds the running sums of A X.
-// LDS: blk [64][65], xi, xj [64][NR].
+// Waves 0 and 2 form the rows of J over the two halves of the block's
+// columns, waves 1 and 3 the rows of I over the two halves of its rows.
+// LDS: blk [64][65], xi, xj, ypart, cpart [64][NR].
 template <int NR>
 __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t lda, int n, int nrhs,
                                          const double* X, const double* B, int64_t ldb, double* R,
@@ -226,6 +228,8 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
   Col* blk = reinterpret_cast<Col*>(pool);                 // blk[q][r] = A(j0 + r, i0 + q)
   double* xi = reinterpret_cast<double*>(pool + 64 * 65 * 8);
   double* xj = xi + 64 * NR;
+  double* ypart = xj + 64 * NR;   // [64][NR]: second halves of the row sums of J
+  double* cpart = ypart + 64 * NR;   // [64][NR]: second halves of the column sums of I
   const int tid = threadIdx.x;
   const int nb = (n + 63) / 64;
   for (int idx = tid; idx < n * nrhs; idx += 256) R[idx] = 0.0;
@@ -286,30 +290,35 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
         if (idx < 64 * NR) xj[q * NR + c] = keep(xc[t], q < nj && c < nrhs);
       }
       __syncthreads();
-      if (tid < 64) {
+      const int wv = tid >> 6, ln = tid & 63;
+      double y[NR];
+      if (wv == 0 || wv == 2) {
         // rows of J: sum over q of A(j0 + r, i0 + q) x_I(q)  (diagonal block: q <= r)
-        const int rr = tid;
-        double y[NR];
+        const int qb = wv == 0 ? 0 : 32;
 #pragma unroll
         for (int c = 0; c < NR; c++) y[c] = 0.0;
-        for (int q = 0; q < 64; q++) {
-          const double a = blk[q][rr];
+        for (int q = qb; q < qb + 32; q++) {
+          const double a = blk[q][ln];
 #pragma unroll
           for (int c = 0; c < NR; c++) y[c] += a * xi[q * NR + c];
         }
-        if (rr < nj)
+        if (wv == 2)
 #pragma unroll
-          for (int c = 0; c < NR; c++)
-            if (c < nrhs) R[(j0 + rr) + (int64_t)c * n] = rs[c] + y[c];
-      } else if (tid < 128) {
+          for (int c = 0; c < NR; c++) ypart[ln * NR + c] = y[c];
+      } else {
         // rows of I: sum over r of A(j0 + r, i0 + q) x_J(r), strictly below the diagonal
-        const int q = tid - 64;
-        for (int rr = 0; rr < 64; rr++) {
+        const int q = ln, rb = wv == 1 ? 0 : 32;
+        for (int rr = rb; rr < rb + 32; rr++) {
           const double a = (J > I || rr > q) ? blk[q][rr] : 0.0;
 #pragma unroll
           for (int c = 0; c < NR; c++) colsum[c] += a * xj[rr * NR + c];
         }
       }
+      __syncthreads();
+      if (wv == 0 && ln < nj)
+#pragma unroll
+        for (int c = 0; c < NR; c++)
+          if (c < nrhs) R[(j0 + ln) + (int64_t)c * n] = rs[c] + (y[c] + ypart[ln * NR + c]);
     };
     {
       double va[16], vb[16], xa[XPT], xb[XPT];
@@ -322,13 +331,16 @@ __device__ __noinline__ void wg_residual(const double* __restrict__ A, int64_t l
       }
       if (J < nb) body(J, va, vb, xa, xb);
     }
+    if (tid >= 192)
+#pragma unroll
+      for (int c = 0; c < NR; c++) cpart[(tid - 192) * NR + c] = colsum[c];
     __syncthreads();
     if (tid >= 64 && tid < 128) {
       const int q = tid - 64;
       if (q < ni)
 #pragma unroll
         for (int c = 0; c < NR; c++)
-          if (c < nrhs) R[(i0 + q) + (int64_t)c * n] += colsum[c];
+          if (c < nrhs) R[(i0 + q) + (int64_t)c * n] += colsum[c] + cpart[q * NR + c];
     }
   }
   __syncthreads();
