@@ -26,6 +26,7 @@ static_assert(kPool >= gemm_q_lds_bytes<_Float16, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<double, 128>(), "pool");
 static_assert(kPool >= gemm_d_lds_bytes<float, 128>(), "pool");
 static_assert(kPool >= cast_lds_bytes<_Float16>(), "pool");
+static_assert(kPool >= 2 * 64 * 65 * 8 + 6 * 64 * 16 * 8, "pool");   // block solves, 16 rhs
 
 __device__ inline int find_job_max(const MaxabsJob* j, int nj, int w) {
   int lo = 0, hi = nj - 1;
@@ -73,16 +74,17 @@ __device__ inline void stage_block(double (*blk)[65], const double* __restrict__
 // X <- L^-1 X (trans 0) or L^-T X (trans 1), n x nrhs (ld n, nrhs <= NR),
 // one workgroup, 64-row blocks.  Off-diagonal blocks: forward, lanes run
 // along the block's rows straight from memory (coalesced); transposed, the
-// block is staged through LDS.  The diagonal block is solved by wave 0 with
-// one lane per row.  LDS: blk, dg [64][65], xs [64][NR], acc [4][64][NR].
+// block is staged through LDS.  The diagonal block is solved one right-hand
+// side per wave, one lane per row.  LDS: blk, dg [64][65], xs [2][64][NR],
+// acc [4][64][NR].
 template <int NR>
 __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, int64_t ldl, int n,
                                      int nrhs, double* X, char* pool) {
   typedef double Col[65];
   Col* blk = reinterpret_cast<Col*>(pool);
   Col* dg = blk + 64;
-  double* xs = reinterpret_cast<double*>(pool + 2 * 64 * 65 * 8);   // [64][NR]
-  double* acc = xs + 64 * NR;                                        // [4][64][NR]
+  double* xs = reinterpret_cast<double*>(pool + 2 * 64 * 65 * 8);   // [2][64][NR]
+  double* acc = xs + 2 * 64 * NR;                                    // [4][64][NR]
   const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int nb = (n + 63) / 64;
   for (int s = 0; s < nb; s++) {
@@ -126,17 +128,22 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
       load_x(min(u + 1, s - 1), xn);
       const int K = trans ? nb - 1 - u : u;
       const int k0 = K * 64, nk = min(64, n - k0);
-      __syncthreads();   // the previous block's readers of xs and blk are done
+      // double-buffered staging (x in xs[u & 1], the transposed block in blk
+      // or, while the diagonal block is not staged yet, dg): the readers of
+      // this buffer two steps back passed the last barrier, so one barrier
+      // per step suffices
+      double* xsb = xs + (u & 1) * 64 * NR;
+      Col* blkb = (u & 1) ? dg : blk;
 #pragma unroll
       for (int t = 0; t < XPT; t++) {
         const int idx = tid + 256 * t, q = idx & 63, c = idx >> 6;
-        if (idx < 64 * NR) xs[q * NR + c] = keep(xc[t], q < nk && c < nrhs);
+        if (idx < 64 * NR) xsb[q * NR + c] = keep(xc[t], q < nk && c < nrhs);
       }
       if (trans) {
 #pragma unroll
         for (int w = 0; w < 16; w++) {
           const int q = g + 4 * w;
-          blk[q][r] = keep(cur[w], r < nk && q < nj);   // blk[q][i] = L(k0 + i, j0 + q)
+          blkb[q][r] = keep(cur[w], r < nk && q < nj);   // blkb[q][i] = L(k0 + i, j0 + q)
         }
       }
       __syncthreads();
@@ -146,15 +153,15 @@ __device__ __noinline__ void wg_trsv(int trans, const double* __restrict__ L, in
           const int q = g + 4 * w;
           const double l = keep(cur[w], r < nj && q < nk);
 #pragma unroll
-          for (int c = 0; c < NR; c++) part[c] += l * xs[q * NR + c];
+          for (int c = 0; c < NR; c++) part[c] += l * xsb[q * NR + c];
         }
       } else {
 #pragma unroll
         for (int w = 0; w < 16; w++) {
           const int i = g + 4 * w;
-          const double l = blk[r][i];
+          const double l = blkb[r][i];
 #pragma unroll
-          for (int c = 0; c < NR; c++) part[c] += l * xs[i * NR + c];
+          for (int c = 0; c < NR; c++) part[c] += l * xsb[i * NR + c];
         }
       }
     };
