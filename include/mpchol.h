@@ -133,7 +133,10 @@ int mpchol_factor(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
                   void* stream, mpchol_info* info);
 
 /*
- * Solve A X = B with the factor L, then refine with FP64 residuals:
+ * Solve A X = B with the factor L, then refine with FP64 residuals (the
+ * paper's abstract names the symmetric linear solve; the refinement is the
+ * classic mixed-precision iterative refinement its related work surveys,
+ * Section 2.2):
  *   x0 = L^-T L^-1 b;  repeat r = b - A x (FP64, A's lower triangle),
  *   d = L^-T L^-1 r, x += d, until max_col ||d||_inf <= tol ||x||_inf, or
  *   max_iter steps, or the correction grows twice in a row.
@@ -271,8 +274,9 @@ int mpchol_backward_error(mpchol_ctx ctx, int64_t n, const double* A, int64_t ld
 
 /* ------------------------------------------------------------------------
  * Learned per-node precision policy.  The paper fixes one precision per
- * recursion level (Section 3.3) and names learned precision selection as
- * future work (Section 6).  Here each internal Tree-POTRF node (Algorithm 1;
+ * recursion level (Section 3.3); a learned per-node choice is this library's
+ * addition on top of that fixed layering (the paper's future work, Section 5,
+ * names dynamic quantization instead).  Here each internal Tree-POTRF node (Algorithm 1;
  * order m > leaf, numbered in preorder like mpchol_tree.node_prec) gets the
  * precision of its Tree-TRSM / Tree-SYRK updates from a 5-64-64-4 perceptron
  * (ReLU, softmax over {E4M3, F16, F32, F64}) evaluated on five features of the

@@ -1,7 +1,8 @@
 """CPU oracle of the learned precision policy (TEST INFRASTRUCTURE ONLY).
 
-The paper fixes one precision per recursion level (Section 3.3) and names
-learned, per-block precision selection as future work (Section 6).  The
+The paper fixes one precision per recursion level (Section 3.3).  A learned
+per-node choice is this project's addition on top of that fixed layering (the
+paper's future work, Section 5, names dynamic quantization instead).  The
 policy built here picks the precision of every internal Tree-POTRF node (the
 node's Tree-TRSM and Tree-SYRK updates, Algorithm 1) from five features of
 the input matrix, with a 5-64-64-4 perceptron.  This module is the plain

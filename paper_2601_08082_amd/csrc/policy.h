@@ -2,9 +2,10 @@
 // and the perceptron's parameter layout, shared by the host planner and the
 // policy kernels.
 //
-// The paper assigns one precision per recursion level (Section 3.3) and
-// leaves learned precision selection to future work (Section 6).  Here every
-// internal Tree-POTRF node (Algorithm 1; preorder numbering, the numbering of
+// The paper assigns one precision per recursion level (Section 3.3); a
+// learned per-node choice is this library's addition on top of that fixed
+// layering (the paper's future work, Section 5, names dynamic quantization
+// instead).  Here every internal Tree-POTRF node (Algorithm 1; preorder numbering, the numbering of
 // the descriptor's per-node override) gets its own precision for its
 // Tree-TRSM / Tree-SYRK updates, chosen by a 5-64-64-4 perceptron from five
 // features of the input matrix.
