@@ -1,12 +1,17 @@
 """Benchmark: mixed-precision nested recursive Cholesky factor + FP64-refined
 solve on one MI355X.
 
-A step is the whole hot path on one synthetic system: Tree-POTRF with
-Tree-TRSM / Tree-SYRK (FP16 levels 0-1, FP32 levels 2-5, FP64 leaves of 256)
-of the 16384 x 16384 dominance-ratio-1.5 SPD matrix, then the substitution
-solve and FP64-residual iterative refinement of one right-hand side to
+A step is the whole hot path on one synthetic system.  The default workload
+is the largest single-GPU configuration: the 65536 x 65536 SPD matrix with
+dominance ratio 1.2 (34 GB in FP64), Tree-POTRF with Tree-TRSM / Tree-SYRK in
+the three-level tree [F16, F32, F64] (level 0 FP16, level 1 FP32, deeper
+levels and the leaves of 256 FP64), then the substitution solve and
+FP64-residual iterative refinement of 16 right-hand sides to
 ||d||_inf <= 1e-13 ||x||_inf.  value = effective TFLOP/s = (n^3/3) / time to
 solution.  Inputs are generated in device memory before the timed region.
+`--workload single` runs the n=16384 configuration (ratio 1.5, tree
+[F16,F16,F32,F32,F32,F32], 1 right-hand side), `--workload batched` the
+4096-system batch.
 
 Prints ONE JSON line (rank 0).  Extra fields: the same step on the all-FP64
 tree (time-to-solution speedup), factor-only rate, the roofline of the
@@ -33,7 +38,9 @@ PEAKS = {"gemm_e4m3": (5000.0, "TFLOP/s", "mfma"), "gemm_f16": (2500.0, "TFLOP/s
          "cast": (8000.0, "GB/s", "hbm"), "maxabs": (8000.0, "GB/s", "hbm"),
          "trsv": (8000.0, "GB/s", "hbm"), "residual": (8000.0, "GB/s", "hbm"),
          "trinv": (78.6, "TFLOP/s", "alu")}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f16_n16384_pmc.md")
+# committed rocprofv3 --pmc summaries of the FP16 GEMM, per workload
+TRAFFIC_FILES = {"large": os.path.join(ROOT, "profiles", "gemm_f16_n65536_pmc.md"),
+                 "single": os.path.join(ROOT, "profiles", "gemm_f16_n16384_pmc.md")}
 GEMM_SRC = [os.path.join(ROOT, "paper_2601_08082_amd", "csrc", f) for f in ("k_gemm.hip", "dev_gemm.h")]
 
 
@@ -46,13 +53,14 @@ def _sha(paths) -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per FP16 GEMM launch from the committed rocprofv3 --pmc
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration);
-    None when the summary is missing or the GEMM source has changed since."""
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, scaled by the
+    copy-kernel calibration); None when the summary is missing or the GEMM
+    source has changed since."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(TRAFFIC_FILES[workload]):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip().lstrip("- ")] = v.strip()
@@ -81,15 +89,16 @@ def _cpu_model() -> str:
     return platform.processor()
 
 
-def cpu_baseline(n_full: int, ratio: float, offdiag, leaf: int, budget_s: float) -> dict:
+def cpu_baseline(n_full: int, ratio: float, offdiag, leaf: int, nrhs: int, budget_s: float) -> dict:
     """The CPU oracle (factor + refined solve) on a bounded sample: the same
-    generator, ratio and tree at a smaller n chosen to take ~budget_s."""
+    generator, ratio, tree and right-hand-side count at a smaller n chosen to
+    take ~budget_s."""
     import oracle as O
     from paper_2601_08082_amd import spdgen
 
     def run(n):
         A = spdgen.gen_spd(n, ratio, 0.0, seed=8)
-        B = spdgen.gen_rhs(n, 1, seed=108)
+        B = spdgen.gen_rhs(n, nrhs, seed=108)
         t0 = time.perf_counter()
         L, st, _ = O.factor(A, tree=O.Tree(leaf=leaf, offdiag=list(offdiag)))
         X, st2, it, _ = O.solve(L, B, A=A, tol=1e-13, max_iter=20)
@@ -105,7 +114,8 @@ def cpu_baseline(n_full: int, ratio: float, offdiag, leaf: int, budget_s: float)
         t = run(n)
     return {"value": (n ** 3 / 3) / t / 1e12, "unit": "TFLOP/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"oracle factor + refined solve at n={n} (same generator, ratio, tree), "
+            "sample": f"oracle factor + refined solve at n={n}, {nrhs} rhs (same generator, ratio, "
+                      f"tree), "
                       f"{t:.1f} s on {_cpu_model()}"}
 
 
@@ -194,15 +204,15 @@ def bench_batched(args) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["single", "large", "batched"], default="single",
-                    help="single: n=16384 ratio 1.5 [F16,F16,F32x4] 1 rhs; large: n=65536 ratio "
-                         "1.2 [F16,F32,F64] 16 rhs; batched: 4096 uneven systems")
+    ap.add_argument("--workload", choices=["large", "single", "batched"], default="large",
+                    help="large: n=65536 ratio 1.2 [F16,F32,F64] 16 rhs (default); single: n=16384 "
+                         "ratio 1.5 [F16,F16,F32x4] 1 rhs; batched: 4096 uneven systems")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--ratio", type=float, default=1.5)
+    ap.add_argument("--n", type=int, default=None, help="order (default: the workload's)")
+    ap.add_argument("--ratio", type=float, default=None, help="dominance ratio (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=16.0)
     ap.add_argument("--no-fp64", action="store_true")
@@ -222,18 +232,16 @@ def main() -> int:
     from paper_2601_08082_amd import mpchol as M
     from paper_2601_08082_amd import spdgen, spdgen_gpu
 
-    n, ratio = args.n, args.ratio
     leaf = 256
-    mixed_levels = [M.F16, M.F16, M.F32, M.F32, M.F32, M.F32]
-    nrhs = 1
     if args.workload == "large":
-        if n == 16384:
-            n = 65536
-        if ratio == 1.5:
-            ratio = 1.2
+        n, ratio, nrhs = 65536, 1.2, 16
         mixed_levels = [M.F16, M.F32, M.F64]
-        nrhs = 16
-        args.no_cpu_baseline = True
+    else:
+        n, ratio, nrhs = 16384, 1.5, 1
+        mixed_levels = [M.F16, M.F16, M.F32, M.F32, M.F32, M.F32]
+    full_size = args.n is None and args.ratio is None
+    n = args.n if args.n is not None else n
+    ratio = args.ratio if args.ratio is not None else ratio
     tree = M.Tree(leaf=leaf, offdiag=mixed_levels, leaf_prec=M.F64)
     tree64 = M.Tree(leaf=leaf, offdiag=[M.F64], leaf_prec=M.F64)
     flops = n ** 3 / 3.0
@@ -318,13 +326,13 @@ def main() -> int:
     roof = {"bound": "mfma", "kernel": "k_gemm_q<f16> (grouped FP16 GEMM/SYRK)",
             "achieved": achieved, "peak": PEAKS["gemm_f16"][0], "unit": "TFLOP/s",
             "frac": achieved / PEAKS["gemm_f16"][0],
-            "traffic": measured_traffic() if (args.workload == "single" and n == 16384) else None,
+            "traffic": measured_traffic(args.workload) if full_size else None,
             "launches_per_step": n16 / args.steps, "ms_per_step": ms16 / args.steps,
             "flops_per_launch": work16 / n16 if n16 else 0.0}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n, ratio, mixed_levels, leaf, args.cpu_budget)
+        cpu = cpu_baseline(n, ratio, mixed_levels, leaf, nrhs, args.cpu_budget)
 
     stats = M.plan_stats(n, tree)
     out = {
@@ -338,7 +346,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16/f32 MFMA (f32 acc) + f64 leaves, f64 in/out",
+        "dtype": ("f16/f32 MFMA (f32 acc) + f64 MFMA levels and leaves, f64 in/out"
+                  if M.F64 in mixed_levels else "f16/f32 MFMA (f32 acc) + f64 leaves, f64 in/out"),
         "data": "synthetic",
         "config": {"workload": f"SPD n={n} dominance ratio {ratio}, tree "
                                f"[{','.join(M.PREC_LABELS[p] for p in mixed_levels)}] "

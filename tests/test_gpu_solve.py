@@ -137,3 +137,39 @@ def test_full_size_16384_mixed_tree(M, ctx):
     lam = spdgen.gershgorin_lower_bound(n, ratio, 0.0, A)
     assert lam > 0
     assert np.linalg.norm(r) / lam <= 1e-12 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("case", ["oscillate", "diverge", "diverge_limit", "nonfinite", "exact"])
+def test_refinement_stopping_rule_matches_oracle(M, ctx, case):
+    """The hand-built systems of the oracle's stopping-rule pins, at n = 200
+    (four 64-row blocks) through the C-ABI: same status, step count and final
+    correction ratio (every step is exact in FP64)."""
+    print(f"[gpu] stopping rule {case}", flush=True)
+    n = 200
+    e = 2.0 ** -20
+    adiag = np.ones(n)
+    ldiag = np.ones(n)
+    b = np.ones(n)
+    max_iter = 20
+    if case == "oscillate":
+        adiag[:] = 2.0
+        max_iter = 5
+    elif case in ("diverge", "diverge_limit"):
+        ldiag[[5, 70, 199]] = 0.5
+        b[[5, 70, 199]] = e
+        max_iter = 20 if case == "diverge" else 2
+    elif case == "nonfinite":
+        b[130] = np.nan
+    else:
+        adiag[:] = 4.0
+        ldiag[:] = 2.0
+    A = np.asfortranarray(np.diag(adiag))
+    L = np.asfortranarray(np.diag(ldiag))
+    B = np.asfortranarray(b.reshape(n, 1))
+    Xo, so, ito, co = O.solve(L, B, A=A, tol=1e-13, max_iter=max_iter)
+    Xd, sinfo = ctx.solve(M.to_device_cm(L), M.to_device_cm(B), n, A_cm=M.to_device_cm(A),
+                          tol=1e-13, max_iter=max_iter)
+    assert sinfo["status"] == so and sinfo["ir_iters"] == ito, (sinfo, so, ito)
+    if so != O.NONFINITE:
+        assert sinfo["final_rel_corr"] == co
+        np.testing.assert_array_equal(M.from_device_cm(Xd)[:n], Xo[:n])
