@@ -43,8 +43,6 @@ struct mpchol_ctx_s {
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
   int64_t rbuf_count = 0;
-  double* resw = nullptr;     // residual tile partials
-  size_t resw_bytes = 0;
   // load-distributed block solves: work items per order, helper partials, flags
   std::map<int64_t, std::pair<int2*, int>> tsv_items;
   double* tsv_p = nullptr;
@@ -602,7 +600,6 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->inv) (void)hipFree(c->inv);
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
-  if (c->resw) (void)hipFree(c->resw);
   for (auto& kv : c->tsv_items) (void)hipFree(kv.second.first);
   if (c->tsv_p) (void)hipFree(c->tsv_p);
   if (c->tsv_flag) (void)hipFree(c->tsv_flag);
@@ -720,7 +717,7 @@ static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
     HIPCHK(hipMalloc((void**)&c->tsv_x, sizeof(double) * xc));
     c->tsv_x_count = xc;
   }
-  if (fc > c->tsv_flag_count || c->tsv_epoch > 0xFFFFFF00u) {
+  if (fc > c->tsv_flag_count || c->tsv_epoch + 64 > trsv2_max_epoch()) {
     // flags only ever hold epochs of earlier calls (or 0): zero them once here
     HIPCHK(hipDeviceSynchronize());
     if (c->tsv_flag) HIPCHK(hipFree(c->tsv_flag));
@@ -807,15 +804,6 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
       HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
       c->rbuf_count = n * nrhs;
     }
-    const size_t wb = residual_work_bytes(n, (int)std::min<int64_t>(kMaxRhs, nrhs));
-    if (c->resw_bytes < wb) {
-      HIPCHK(hipStreamSynchronize(s));
-      if (c->resw) HIPCHK(hipFree(c->resw));
-      c->resw = nullptr;
-      c->resw_bytes = 0;
-      HIPCHK(hipMalloc((void**)&c->resw, wb));
-      c->resw_bytes = wb;
-    }
     double* R = c->rbuf;
     double prev = INFINITY;
     int grew = 0;
@@ -826,7 +814,7 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
         int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_RESIDUAL,
                                            (double)n * (n + 1) / 2 * 8.0, s) : -1;
         HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
-                               c->resw, s));
+                               s));
         prof_end(c, pk, s);
       }
       r = chol_solve_inplace(c, n, nrhs, L, ldl, R, n, s);

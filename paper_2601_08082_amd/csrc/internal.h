@@ -114,17 +114,18 @@ hipError_t launch_trsm_leaf(int prec, double* Lm, int64_t ldl, int64_t r0, int64
 hipError_t launch_diag_inv(const double* Lm, int64_t ldl, int64_t n, double* Yd, hipStream_t s);
 
 // Solve / refinement kernels.
-// R = B - A X (A symmetric, lower stored, read once); work holds
-// residual_work_bytes(n, nrhs) bytes of tile partials.
-size_t residual_work_bytes(int64_t n, int nrhs);
+// R = B - A X (A symmetric, lower stored; one workgroup per 64-row block of R
+// reads its row and its column of tiles, no workspace).
 // Load-distributed block solve: ticketed diagonal and helper items (the list
-// from trsv2_items), helper partial sums in P (trsv2_partial_doubles(n)) with
-// epoch-tagged flags (trsv2_flags(n) words, zero before first use), and XP
+// from trsv2_items), running helper partial sums in P (trsv2_partial_doubles(n))
+// with epoch-tagged flags (trsv2_flags(n) words, zero before first use), and XP
 // (n x nrhs doubles, ld n) for the published solution blocks.  Yd holds the
 // inverses of the 64 x 64 diagonal blocks (launch_diag_inv).
 int trsv2_items(int64_t n, std::vector<int2>& items);
 size_t trsv2_partial_doubles(int64_t n);
 size_t trsv2_flags(int64_t n);
+// largest epoch a flag tag can carry (flags are zeroed and epochs restart below it)
+unsigned int trsv2_max_epoch();
 hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
                         int64_t ldx, double* XP, const double* Yd, const int2* items, int nitems,
                         double* P,
@@ -132,7 +133,7 @@ hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int
                         hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
-                           double* work, hipStream_t s);
+                           hipStream_t s);
 hipError_t launch_update_norms(int64_t n, int nrhs, double* X, int64_t ldx, const double* D,
                                int64_t ldd, double* part, int nparts, double* out,
                                hipStream_t s);
