@@ -54,10 +54,10 @@ __device__ inline int xcd_tile(int w, int total) {
 __device__ inline double reduce_max(const double* __restrict__ part, int p0, int np,
                                     double* red) {
   double m = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) m = fmax(m, part[p0 + i]);
-  red[threadIdx.x] = m;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) m = fmax(m, part[p0 + i]);
+  red[threadIdx.x] = m;   // red holds blockDim.x (a power of two) entries
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = (int)blockDim.x >> 1; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
@@ -140,14 +140,16 @@ __device__ inline uint4 direct_chunk(const double* __restrict__ Lm, int64_t ldl,
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// One output tile t of problem P (workgroup-level; lds = gemm_q_lds_bytes()).
+// The output tile with origin (m0, n0) of problem P, given the block scales
+// (sxy = sx sy; isx, isy their inverses) and whether each operand is
+// quantized from the factor on the way in (its block scale is not 1).
+// Workgroup-level; lds = gemm_q_lds_bytes().
 template <typename Q, int BM>
-__device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
-                                   const Q* __restrict__ ws, const GemmProb& P, int t,
-                                   const double* __restrict__ part, int prec, int scale_mode,
-                                   DevStatus* st, char* lds) {
+__device__ __attribute__((always_inline)) inline void gemm_q_tile_at(double* __restrict__ Lm, int64_t ldl,
+                                      const Q* __restrict__ ws, const GemmProb& P, int m0, int n0,
+                                      double sxy, double isx, double isy, bool xdir, bool ydir,
+                                      int prec, char* lds) {
   typedef typename QOps<Q>::vec vec;
-  constexpr int BN = BM;                         // square tiles: 128 or 64
   constexpr int WT = BM / 2;                     // wave tile (2 x 2 waves)
   constexpr int NF = WT / 32;                    // 32 x 32 MFMA tiles per wave dimension
   constexpr int CPR = gemm_q_kbytes<BM>() / 16;  // 16-byte chunks per row and K step
@@ -158,21 +160,10 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
   typedef Q QTile[BM * LDSW];
   QTile* Xs = reinterpret_cast<QTile*>(lds);
   QTile* Ys = Xs + 2;
-  double* red = reinterpret_cast<double*>(Ys + 2);
-  __syncthreads();   // the pool may still be in use by the previous task
+  __syncthreads();   // the pool may still be in use
 
-  int tm, tn;
-  tile_coords(P, t, &tm, &tn);
-  double isx, isy;
-  const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
-
-  const int m0 = tm * BM, n0 = tn * BN;
   const Q* __restrict__ X = ws + P.x;
   const Q* __restrict__ Y = ws + P.y;
-  // a single-pass operand (xsrc >= 0) whose block scale is not 1 is
-  // quantized from the factor on the way in (rare; its scale-1 copy does
-  // not apply)
-  const bool xdir = P.xsrc >= 0 && isx != 1.0, ydir = P.ysrc >= 0 && isy != 1.0;
   const bool direct = xdir || ydir;   // uniform
   const int kv = (P.k + 15) & ~15;  // zero-padded K extent of the copies
   const int nk = (kv + BK - 1) / BK;
@@ -298,6 +289,224 @@ __device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
           C[m + (int64_t)n * ldl] = cv[b][r] - sxy * (double)acc[a][b][r];
       }
     }
+  }
+}
+
+// One output tile t of problem P (workgroup-level; lds = gemm_q_lds_bytes()).
+template <typename Q, int BM>
+__device__ inline void gemm_q_tile(double* __restrict__ Lm, int64_t ldl,
+                                   const Q* __restrict__ ws, const GemmProb& P, int t,
+                                   const double* __restrict__ part, int prec, int scale_mode,
+                                   DevStatus* st, char* lds) {
+  double* red = reinterpret_cast<double*>(lds + 2 * 2 * BM * (gemm_q_kbytes<BM>() + 16));
+  __syncthreads();   // the pool may still be in use by the previous task
+  int tm, tn;
+  tile_coords(P, t, &tm, &tn);
+  double isx, isy;
+  const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
+  // a single-pass operand (xsrc >= 0) whose block scale is not 1 is
+  // quantized from the factor on the way in (rare; its scale-1 copy does
+  // not apply)
+  const bool xdir = P.xsrc >= 0 && isx != 1.0, ydir = P.ysrc >= 0 && isy != 1.0;
+  gemm_q_tile_at<Q, BM>(Lm, ldl, ws, P, tm * BM, tn * BM, sxy, isx, isy, xdir, ydir, prec, lds);
+}
+
+// ------------------------------------------------------------------------
+// FP16 operands, 256 x 256 output tiles for large groups: eight waves (two
+// per SIMD) of 128 x 64, i.e. 4 x 2 fragments of v_mfma_f32_32x32x16_f16, K
+// steps of 64.  Operand rows go from the workspace copies straight into LDS
+// (buffer_load ... lds, no VGPR staging and no LDS store instructions), two
+// stages: the loads of step k + 1 are issued at the start of step k.  Inside a
+// 128-byte row the eight 16-byte chunks are XOR-swizzled with the row
+// (q256_swz), so that the fragment reads (32 consecutive rows, one chunk each)
+// fall into distinct banks; each direct load instruction covers eight whole
+// rows (eight lanes per row, permuted), so it stays fully coalesced.  Requires
+// K % 64 == 0 (no padding to mask) and operand blocks below 2 GB (32-bit
+// buffer offsets); the plan only picks this tile when both hold.
+constexpr int kQ256Stage = 2 * 256 * 128;   // bytes of one stage: X rows, then Y rows
+constexpr int gemm_q256_lds_bytes() { return 2 * kQ256Stage; }
+constexpr int kQ256Threads = 512;
+
+__device__ inline int q256_swz(int row) { return ((row >> 1) ^ ((row & 1) << 2)) & 7; }
+
+// a buffer resource over `p` (uniform): raw, untyped dword access
+__device__ inline __amdgpu_buffer_rsrc_t q256_rsrc(const void* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* u = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, 0, 0x7fffffff, 0x00020000);
+}
+
+template <typename Q>
+__device__ inline void gemm_q256_tile(double* __restrict__ Lm, int64_t ldl,
+                                      const Q* __restrict__ ws, const GemmProb& P, int t,
+                                      const double* __restrict__ part, int prec, int scale_mode,
+                                      DevStatus* st, char* lds) {
+  static_assert(sizeof(Q) == 2, "FP16 operands");
+  typedef typename QOps<Q>::vec vec;
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int BM = 256, BK = 64;
+  constexpr int WM = 128, WN = 64;            // wave tile (2 x 4 waves)
+  constexpr int FM = WM / 32, FN = WN / 32;   // fragments per wave
+  double* red = reinterpret_cast<double*>(lds);
+  __syncthreads();
+  int tm, tn;
+  tile_coords(P, t, &tm, &tn);
+  double isx, isy;
+  const double sxy = operand_scales(P, part, prec, scale_mode, st, red, &isx, &isy);
+  const bool xdir = P.xsrc >= 0 && isx != 1.0, ydir = P.ysrc >= 0 && isy != 1.0;
+  const int m0 = tm * BM, n0 = tn * BM;
+  // the wave index made uniform: the LDS destination of a direct load (M0)
+  // must be a scalar
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const int nk = max(1, P.k / BK);
+
+  f32x16 acc[FN][FM];
+#pragma unroll
+  for (int a = 0; a < FN; a++)
+#pragma unroll
+    for (int b = 0; b < FM; b++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[a][b][r] = 0.0f;
+  auto fmul = [&](const vec (&fa)[FN], const vec (&fb)[FM]) {
+#pragma unroll
+    for (int a = 0; a < FN; a++)
+#pragma unroll
+      for (int b = 0; b < FM; b++) acc[a][b] = QOps<Q>::mfma(fa[a], fb[b], acc[a][b]);
+  };
+
+  if (xdir || ydir) {
+    // rare (a block scale is not 1): every wave forms its fragments straight
+    // from global memory, the operand with the odd scale quantized from the
+    // factor on the way in (no LDS, no barriers)
+    const Q* __restrict__ X = ws + P.x;
+    const Q* __restrict__ Y = ws + P.y;
+#pragma unroll 1
+    for (int k0 = 0; k0 < P.k; k0 += 16) {
+      const int kc = k0 + 8 * (lane >> 5);
+      vec fa[FN], fb[FM];
+#pragma unroll
+      for (int a = 0; a < FN; a++) {
+        const int row = min(n0 + wn * WN + a * 32 + (lane & 31), P.n - 1);
+        const uint4 u = ydir ? direct_chunk<Q>(Lm, ldl, P.ysrc, row, kc, P.k, isy, prec)
+                             : *reinterpret_cast<const uint4*>(Y + (int64_t)row * P.ldy + kc);
+        fa[a] = __builtin_bit_cast(vec, u);
+      }
+#pragma unroll
+      for (int b = 0; b < FM; b++) {
+        const int row = min(m0 + wm * WM + b * 32 + (lane & 31), P.m - 1);
+        const uint4 u = xdir ? direct_chunk<Q>(Lm, ldl, P.xsrc, row, kc, P.k, isx, prec)
+                             : *reinterpret_cast<const uint4*>(X + (int64_t)row * P.ldx + kc);
+        fb[b] = __builtin_bit_cast(vec, u);
+      }
+      fmul(fa, fb);
+    }
+  } else {
+
+  // direct loads: wave w, instruction i fills the 1 KB at unit (4 w + i) * 64
+  // of an operand's 32 KB stage block; lane l takes row 32 w + 8 i + l / 8,
+  // stored chunk l % 8, i.e. source chunk (l % 8) ^ swz(row).  The operand
+  // block is the (uniform) buffer resource, the lane's row and chunk a 32-bit
+  // offset fixed for the whole loop, the K step the scalar offset.
+  uint32_t gx[4], gy[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int row = 32 * wave + 8 * i + (lane >> 3);
+    const int c = (lane & 7) ^ q256_swz(row);
+    gx[i] = (uint32_t)(((int64_t)min(m0 + row, P.m - 1) * P.ldx + 8 * c) * 2);
+    gy[i] = (uint32_t)(((int64_t)min(n0 + row, P.n - 1) * P.ldy + 8 * c) * 2);
+  }
+  const __amdgpu_buffer_rsrc_t rx = q256_rsrc(ws + P.x);
+  const __amdgpu_buffer_rsrc_t ry = q256_rsrc(ws + P.y);
+  auto issue = [&](int kt, char* stage) {
+    const int ko = __builtin_amdgcn_readfirstlane(kt * BK * 2);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_ptr)(stage + (4 * wave + i) * 1024), 16,
+                                               gx[i], ko, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)(stage + 32768 + (4 * wave + i) * 1024),
+                                               16, gy[i], ko, 0, 0);
+    }
+  };
+
+  // fragment reads: lane l reads row base + l % 32, chunk 2 kk + l / 32
+  const int swz = q256_swz(lane & 31);
+  const uint32_t rowoff = (uint32_t)(lane & 31) * 128;
+  vec af[2][FN], bf[2][FM];
+  auto fread = [&](const char* stage, int kk, vec (&fa)[FN], vec (&fb)[FM]) {
+    const uint32_t co = (uint32_t)(((2 * kk + (lane >> 5)) ^ swz) << 4);
+#pragma unroll
+    for (int a = 0; a < FN; a++)
+      fa[a] = *reinterpret_cast<const vec*>(stage + 32768 + (wn * WN + a * 32) * 128 + rowoff + co);
+#pragma unroll
+    for (int b = 0; b < FM; b++)
+      fb[b] = *reinterpret_cast<const vec*>(stage + (wm * WM + b * 32) * 128 + rowoff + co);
+  };
+  // One K step out of `stage` (its sub-step 0 fragments already read) while
+  // the next step's rows load into `next`; ends with the next step's sub-step
+  // 0 fragments read.
+  auto kstep = [&](const char* stage, char* next, int kload) {
+    issue(kload, next);
+    fread(stage, 1, af[1], bf[1]);
+    fmul(af[0], bf[0]);
+    fread(stage, 2, af[0], bf[0]);
+    fmul(af[1], bf[1]);
+    fread(stage, 3, af[1], bf[1]);
+    fmul(af[0], bf[0]);
+    fmul(af[1], bf[1]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    fread(next, 0, af[0], bf[0]);
+  };
+
+  char* S0 = lds;
+  char* S1 = lds + kQ256Stage;
+  __syncthreads();   // the scale reduction is done with the pool
+  issue(0, S0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  fread(S0, 0, af[0], bf[0]);
+  // nk >= 1: a loop that may run zero times would keep a second (all-zero)
+  // copy of the accumulators alive for the skipped path
+  int kt = 0;
+  do {
+    // past the end a step reloads the last K block into the free stage
+    kstep(S0, S1, min(kt + 1, nk - 1));
+    if (kt + 1 < nk) kstep(S1, S0, min(kt + 2, nk - 1));
+    kt += 2;
+  } while (kt < nk);
+  }
+
+  // C tile, one 32 x 32 fragment at a time: the next fragment's 16 loads are
+  // issued (addresses clamped into the block) before this one's stores
+  double* __restrict__ C = Lm + P.c;
+  auto cload = [&](int a, int b, double (&cv)[16]) {
+    const int m = min(m0 + wm * WM + b * 32 + (lane & 31), P.m - 1);
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int n = min(n0 + wn * WN + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), P.n - 1);
+      cv[r] = C[m + (int64_t)n * ldl];
+    }
+  };
+  auto cstore = [&](int a, int b, const double (&cv)[16]) {
+    const int m = m0 + wm * WM + b * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int n = n0 + wn * WN + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (m < P.m && n < P.n && (!P.lower || m >= n))
+        C[m + (int64_t)n * ldl] = cv[r] - sxy * (double)acc[a][b][r];
+    }
+  };
+  double c0[16], c1[16];
+  cload(0, 0, c0);
+#pragma unroll
+  for (int f = 0; f < FN * FM; f += 2) {
+    cload((f + 1) / FM, (f + 1) % FM, c1);
+    cstore(f / FM, f % FM, c0);
+    if (f + 2 < FN * FM) cload((f + 2) / FM, (f + 2) % FM, c0);
+    cstore((f + 1) / FM, (f + 1) % FM, c1);
   }
 }
 

@@ -7,8 +7,7 @@
 // (Section 3.3 layering; Section 3.4 dequantization by the block scales).
 // One launch handles a list of independent problems; every workgroup owns one
 // output tile (64 or 128 square; 32 for small FP32 / FP64 groups) of one
-// problem.  The bodies live in
-// dev_gemm.h.
+// problem (256 for large FP16 groups).  The bodies live in dev_gemm.h.
 //
 // Output orientation: the MFMA computes D = Y X^T so that the lane index runs
 // along C's rows, which are contiguous in the column-major factor.
@@ -26,6 +25,17 @@ __global__ __launch_bounds__(256) void k_gemm_q(double* __restrict__ Lm, int64_t
   const int w = xcd_tile(blockIdx.x, gridDim.x);
   const GemmProb P = probs[find_prob(probs, nprobs, w)];
   gemm_q_tile<Q, BM>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
+}
+
+__global__ __launch_bounds__(kQ256Threads) void k_gemm_q256(double* __restrict__ Lm, int64_t ldl,
+                                                   const _Float16* __restrict__ ws,
+                                                   const GemmProb* __restrict__ probs, int nprobs,
+                                                   const double* __restrict__ part, int prec,
+                                                   int scale_mode, DevStatus* st) {
+  __shared__ __attribute__((aligned(16))) char pool[gemm_q256_lds_bytes()];
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb P = probs[find_prob(probs, nprobs, w)];
+  gemm_q256_tile<_Float16>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
 }
 
 template <int BM>
@@ -80,7 +90,10 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
                        int scale_mode, DevStatus* st, hipStream_t s) {
   if (nprobs <= 0 || total_tiles <= 0) return hipSuccess;
   dim3 g(total_tiles), b(256);
-  if (tile == 64) {
+  if (tile == 256 && prec == F16) {
+    hipLaunchKernelGGL(k_gemm_q256, g, dim3(kQ256Threads), 0, s, Lm, ldl, (const _Float16*)ws, probs,
+                       nprobs, part, prec, scale_mode, st);
+  } else if (tile == 64) {
     launch_gemm_bm<64>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
   } else if (tile == 128) {
     launch_gemm_bm<128>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);

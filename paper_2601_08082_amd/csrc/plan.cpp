@@ -14,7 +14,8 @@
 //  - a leaf of the precision tree larger than the kernel leaf (128) is factored
 //    / solved by an all-leaf-precision sub-recursion down to 128; this is a
 //    leaf-precision Cholesky (resp. triangular solve) of that leaf;
-//  - GEMM launches use 128 x 128 output tiles, or 64 x 64 when 128-tiles would
+//  - GEMM launches use 128 x 128 output tiles (256 x 256 for large FP16
+//    groups), or 64 x 64 when 128-tiles would
 //    leave most of the 256 compute units idle.
 #include "plan.h"
 
@@ -381,11 +382,20 @@ struct Builder {
         for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
         L.tile = mn >= 128 ? 128 : 64;
       } else {
-        // 128 x 128 tiles unless that leaves most of the 256 CUs idle (256 x
-        // 256 tiles measured slower: one wave per SIMD, fewer loads in flight);
-        // FP32 / FP64 groups with fewer than 256 64-tiles take 32-tiles
+        // 128 x 128 tiles unless that leaves most of the 256 CUs idle; FP32 /
+        // FP64 groups with fewer than 256 64-tiles take 32-tiles.  Large FP16
+        // groups take the 256 x 256 kernel (operands loaded straight into
+        // LDS), which needs K % 64 == 0 and operand blocks addressable with
+        // 31-bit byte offsets
         L.tile = tiles_of(128) >= 256 ? 128 : 64;
         if (L.tile == 64 && (prec == F32 || prec == F64) && tiles_of(64) < 256) L.tile = 32;
+        if (prec == F16 && tiles_of(256) >= 256) {
+          bool ok = true;
+          for (auto& g : gp)
+            ok = ok && g.k % 64 == 0 && (int64_t)g.m * g.ldx * 2 < ((int64_t)1 << 31) &&
+                 (int64_t)g.n * g.ldy * 2 < ((int64_t)1 << 31);
+          if (ok) L.tile = 256;
+        }
       }
       int tiles = 0;
       for (auto& g : gp) {

@@ -22,7 +22,7 @@ struct Launch {
                                           // substitution)
   int64_t off = 0;                        // POTRF / TRINV / TRSM: element offset in the slot
                                           // (INVJOIN: a0 = i0, a1 = m, a2 = m1)
-  int tile = 128;                         // GEMM output tile (64 or 128)
+  int tile = 128;                         // GEMM output tile (32, 64, 128 or 256)
 };
 
 struct PlanStats {
