@@ -43,17 +43,12 @@ struct mpchol_ctx_s {
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
   int64_t rbuf_count = 0;
-  // load-distributed block solves: work items per order, helper partials, flags
-  std::map<int64_t, std::pair<int2*, int>> tsv_items;
-  double* tsv_p = nullptr;
-  size_t tsv_p_count = 0;
-  unsigned int* tsv_flag = nullptr;
-  size_t tsv_flag_count = 0;
+  // block solves: published solution blocks and diagonal-block inverses
   double* tsv_x = nullptr;    // published solution blocks (n x kMaxRhs)
   size_t tsv_x_count = 0;
-  double* tsv_yd = nullptr;   // inverses of the 64 x 64 diagonal blocks of L
+  double* tsv_yd = nullptr;   // inverses of the 64 x 64 diagonal blocks of L, then
+                              // the chain-step matrices of both solve directions
   size_t tsv_yd_count = 0;
-  unsigned int tsv_epoch = 0;
   double* npart = nullptr;    // norm partials (device)
   double* hnpart = nullptr;   // norm partials (pinned host)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -600,9 +595,6 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->inv) (void)hipFree(c->inv);
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
-  for (auto& kv : c->tsv_items) (void)hipFree(kv.second.first);
-  if (c->tsv_p) (void)hipFree(c->tsv_p);
-  if (c->tsv_flag) (void)hipFree(c->tsv_flag);
   if (c->tsv_x) (void)hipFree(c->tsv_x);
   if (c->tsv_yd) (void)hipFree(c->tsv_yd);
   if (c->npart) (void)hipFree(c->npart);
@@ -677,29 +669,9 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
   return status_from(*c->hst, info);
 }
 
-// Work items, helper partials and flags of the block solves of order n.
-static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
-  auto it = c->tsv_items.find(n);
-  if (it == c->tsv_items.end()) {
-    std::vector<int2> v;
-    trsv2_items(n, v);
-    int2* d = nullptr;
-    HIPCHK(hipMalloc((void**)&d, sizeof(int2) * v.size()));
-    HIPCHK(hipMemcpy(d, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice));
-    it = c->tsv_items.emplace(n, std::make_pair(d, (int)v.size())).first;
-  }
-  *items = it->second.first;
-  *nitems = it->second.second;
-  const size_t pc = trsv2_partial_doubles(n), fc = trsv2_flags(n);
-  if (pc > c->tsv_p_count) {
-    HIPCHK(hipDeviceSynchronize());
-    if (c->tsv_p) HIPCHK(hipFree(c->tsv_p));
-    c->tsv_p = nullptr;
-    c->tsv_p_count = 0;
-    HIPCHK(hipMalloc((void**)&c->tsv_p, sizeof(double) * pc));
-    c->tsv_p_count = pc;
-  }
-  const size_t yc = (size_t)((n + 63) / 64) * 4096;
+// Published-block copy and diagonal-block inverses of the block solves of order n.
+static int ensure_trsv(mpchol_ctx c, int64_t n) {
+  const size_t yc = (size_t)((n + 63) / 64) * 4096 * 3;
   if (yc > c->tsv_yd_count) {
     HIPCHK(hipDeviceSynchronize());
     if (c->tsv_yd) HIPCHK(hipFree(c->tsv_yd));
@@ -717,18 +689,6 @@ static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
     HIPCHK(hipMalloc((void**)&c->tsv_x, sizeof(double) * xc));
     c->tsv_x_count = xc;
   }
-  if (fc > c->tsv_flag_count || c->tsv_epoch + 64 > trsv2_max_epoch()) {
-    // flags only ever hold epochs of earlier calls (or 0): zero them once here
-    HIPCHK(hipDeviceSynchronize());
-    if (c->tsv_flag) HIPCHK(hipFree(c->tsv_flag));
-    c->tsv_flag = nullptr;
-    c->tsv_flag_count = 0;
-    HIPCHK(hipMalloc((void**)&c->tsv_flag, sizeof(unsigned int) * fc));
-    HIPCHK(hipMemset(c->tsv_flag, 0, sizeof(unsigned int) * fc));
-    HIPCHK(hipDeviceSynchronize());
-    c->tsv_flag_count = fc;
-    c->tsv_epoch = 0;
-  }
   return 0;
 }
 
@@ -737,23 +697,19 @@ static int ensure_trsv(mpchol_ctx c, int64_t n, int2** items, int* nitems) {
 static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
   const double lbytes = (double)n * (n + 1) / 2 * 8.0;
-  int2* items = nullptr;
-  int nitems = 0;
-  int r = ensure_trsv(c, n, &items, &nitems);
+  int r = ensure_trsv(c, n);
   if (r) return r;
+  int rows = 0;
+  const int P = trsv_grid(n, c->device, &rows);
+  if (P <= 0) return MPCHOL_HIP_ERROR;
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
-    HIPCHK(launch_ticket_reset(c->dst, s));
-    int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv2(0, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd, items, nitems, c->tsv_p,
-                        c->tsv_flag,
-                        ++c->tsv_epoch, c->dst, 0, s));
-    prof_end(c, pk, s);
-    pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-    HIPCHK(launch_trsv2(1, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd, items, nitems, c->tsv_p,
-                        c->tsv_flag,
-                        ++c->tsv_epoch, c->dst, 2, s));
-    prof_end(c, pk, s);
+    for (int trans = 0; trans < 2; trans++) {
+      const int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
+      HIPCHK(launch_trsv(trans, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd,
+                         c->tsv_yd + (size_t)((n + 63) / 64) * 4096, P, rows, c->dst, s));
+      prof_end(c, pk, s);
+    }
   }
   return 0;
 }
@@ -780,15 +736,14 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
   HIPCHK(launch_status_init(c->dst, s));
   HIPCHK(launch_copy_cols(n, (int)nrhs, B, ldb, X, ldx, s));
   {
-    int2* items = nullptr;
-    int nitems = 0;
-    int r0 = ensure_trsv(c, n, &items, &nitems);
+    int r0 = ensure_trsv(c, n);
     if (r0) return r0;
     // used by every triangular solve of this call
     const int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRINV,
                                              (double)((n + 63) / 64) * 64.0 * 64.0 * 64.0 / 3.0, s)
                                 : -1;
     HIPCHK(launch_diag_inv(L, ldl, n, c->tsv_yd, s));
+    HIPCHK(launch_chain_mats(L, ldl, n, c->tsv_yd, c->tsv_yd + (size_t)((n + 63) / 64) * 4096, s));
     prof_end(c, pk, s);
   }
   int r = chol_solve_inplace(c, n, nrhs, L, ldl, X, ldx, s);

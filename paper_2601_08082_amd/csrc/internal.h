@@ -116,21 +116,19 @@ hipError_t launch_diag_inv(const double* Lm, int64_t ldl, int64_t n, double* Yd,
 // Solve / refinement kernels.
 // R = B - A X (A symmetric, lower stored; one workgroup per 64-row block of R
 // reads its row and its column of tiles, no workspace).
-// Load-distributed block solve: ticketed diagonal and helper items (the list
-// from trsv2_items), running helper partial sums in P (trsv2_partial_doubles(n))
-// with epoch-tagged flags (trsv2_flags(n) words, zero before first use), and XP
-// (n x nrhs doubles, ld n) for the published solution blocks.  Yd holds the
-// inverses of the 64 x 64 diagonal blocks (launch_diag_inv).
-int trsv2_items(int64_t n, std::vector<int2>& items);
-size_t trsv2_partial_doubles(int64_t n);
-size_t trsv2_flags(int64_t n);
-// largest epoch a flag tag can carry (flags are zeroed and epochs restart below it)
-unsigned int trsv2_max_epoch();
-hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
-                        int64_t ldx, double* XP, const double* Yd, const int2* items, int nitems,
-                        double* P,
-                        unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
-                        hipStream_t s);
+// Block solves (forward trans = 0, backward trans = 1) of up to 16 right-hand
+// sides in place in X: a persistent grid of P workgroups (trsv_grid; all
+// resident at once, launched cooperatively), each owning `rows` 64-row blocks
+// (their running sums in LDS).  XP (n x nrhs doubles, ld n) receives the
+// published solution blocks; Yd holds the inverses of the 64 x 64 diagonal
+// blocks (launch_diag_inv) and Md (2 nblk 4096 doubles) the chain-step
+// matrices (launch_chain_mats).
+int trsv_grid(int64_t n, int device, int* rows_per_wg);
+hipError_t launch_chain_mats(const double* Lm, int64_t ldl, int64_t n, const double* Yd,
+                             double* Md, hipStream_t s);
+hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
+                       int64_t ldx, double* XP, const double* Yd, const double* Md, int P,
+                       int rows, DevStatus* st, hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
                            hipStream_t s);

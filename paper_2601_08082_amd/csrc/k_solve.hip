@@ -1,7 +1,7 @@
 // Solve and FP64-residual iterative refinement kernels:
-//   - blocked triangular solves L y = b and L^T x = y over 64-row blocks:
-//     ticketed diagonal and helper work items (see k_trsv3), every wait a
-//     bounded spin on an item with a smaller ticket;
+//   - blocked triangular solves L y = b and L^T x = y over 64-row blocks: a
+//     persistent right-looking grid (k_trsv5), every wait a bounded spin on a
+//     value published by a resident workgroup;
 //   - the FP64 residual R = B - A X with A symmetric and only its lower
 //     triangle read;
 //   - X += D with per-column max-abs of D and X for the stopping rule.
@@ -58,18 +58,64 @@ __device__ inline int kmap(bool trans, int t, int g) { return trans ? 16 * g + t
 // the workgroup) and the offsets are 32-bit (a tile spans less than 64 ld
 // elements).  Addresses are clamped into the valid no x nk part; the clamped
 // values are masked in tile_mfma.
+// a raw buffer resource over a tile (a tile spans less than 2^31 bytes)
+__device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const double* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0,
+                                           0x7fffffff, 0x00020000);
+}
+
 __device__ inline void tile_load(const double* __restrict__ T, uint32_t so, uint32_t sk, bool trans,
                                  bool mirror, int no, int nk, double (&v)[16]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
-  const uint32_t o = (uint32_t)min(16 * w + (l & 15), no - 1);
   const char* __restrict__ Tb = reinterpret_cast<const char*>(T);
   const uint32_t bso = so * 8u, bsk = sk * 8u;   // byte strides
+  if (!mirror && no == NB && nk == NB) {
+    // a whole tile (uniform): one lane offset for all 16 loads, the load index
+    // a uniform step (forward: 4 columns; transposed: one row, an immediate)
+    // buffer loads: the tile's first element is the (uniform) base, the lane
+    // offset one VGPR, the step of load t a scalar offset
+    const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(trans ? 16 * g : g) * bsk;
+    const uint32_t st = trans ? bsk : 4u * bsk;
+    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(T);
+#pragma unroll
+    for (int t = 0; t < 16; t++)
+      v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                            rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(t * st), 0));
+    return;
+  }
+  const uint32_t o = (uint32_t)min(16 * w + (l & 15), no - 1);
 #pragma unroll
   for (int t = 0; t < 16; t++) {
     const uint32_t k = (uint32_t)min(kmap(trans, t, g), nk - 1);
     const uint32_t r = mirror ? max(o, k) : o, c = mirror ? min(o, k) : k;
     v[t] = *reinterpret_cast<const double*>(Tb + (r * bso + c * bsk));
   }
+}
+
+// The same 16 elements by buffer loads from a tile that may extend past the
+// matrix (a ragged last block): no clamping, so every call issues the same 16
+// loads with one lane offset; reads at or beyond `limit` bytes from T return
+// zero, the others past the block's edge return whatever the buffer holds
+// there (masked in tile_mfma, or landing in output rows nobody stores).
+__device__ inline void tile_load_b(const double* __restrict__ T, uint32_t so, uint32_t sk,
+                                   bool trans, uint32_t limit, double (&v)[16]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
+  const uint32_t bso = so * 8u, bsk = sk * 8u;
+  const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(trans ? 16 * g : g) * bsk;
+  const uint32_t st = trans ? bsk : 4u * bsk;
+  const uint64_t a = reinterpret_cast<uint64_t>(T);
+  const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(((uint64_t)ahi << 32) | alo), 0,
+      (int)__builtin_amdgcn_readfirstlane(limit), 0x00020000);
+#pragma unroll
+  for (int t = 0; t < 16; t++)
+    v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                          rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(t * st), 0));
 }
 
 // acc += tile (no x nk valid) times the staged block xs (k x 16, row stride
@@ -99,59 +145,54 @@ __device__ inline void xblock_coords(int nrows, int nrhs, int (&cidx)[4], int& i
 }
 
 // ------------------------------------------------------------------------
-// Load-distributed block solve L y = b (trans = 0) or L^T x = y (trans = 1)
-// over 64-row blocks, taken in solve order s (forward: block J = s; backward:
-// J = nblk - 1 - s).  Work items, handed out by ticket in a dependency-safe
-// order (every wait is on an item with a smaller ticket):
-//   D(s)     diagonal item: the blocks K of its window, CW (s / CW) - CW up to
-//            s - 1, as their solutions are published (so the last dependency
-//            costs one hop), plus the running partial P[s] of the chunks
-//            before the window; then x_s = Y_s (b_s - sum), Y_s the inverse of
-//            the diagonal block, and publishes x_s;
-//   T(s, c)  helper: the CW blocks K of chunk c of row s, added to the running
-//            partial P[s] left by T(s, c - 1), written back and flagged.
-// Each block of L is read once per solve, by one item; a row's partial sums
-// are added in chunk order, so the result is deterministic.  Solved blocks
-// are published by agent-scope atomic stores into a copy that was filled
-// with a sentinel before the launch; readers poll the values themselves
+// Block solve L y = b (trans = 0) or L^T x = y (trans = 1) over 64-row blocks,
+// taken in solve order s (forward: block J = s; backward: J = nblk - 1 - s),
+// right-looking: once block k is solved, every later block s > k takes
+// L(s, k) y_k (backward: L(k, s)^T x_k) into its running sum
+// r_s = b_s - sum.  Block s's own chain step is split so that only one
+// 64 x 64 product waits for its predecessor:
+//   z_s = Y_s r_s with the products of all blocks but s - 1 (the inverse Y_s
+//         of the diagonal block; backward Y_s^T), formed as soon as r_s has
+//         them, off the chain;
+//   x_s = z_s - M_s x_{s-1}, M_s = Y_s L(s, s - 1) (backward
+//         Y_s^T L(s - 1, s)^T, in solve order), precomputed per block.
+// Equal to x_s = Y_s r_s up to rounding.
+//
+// A persistent grid of P co-resident workgroups; workgroup o owns the blocks
+// s = o + j P, their running sums in LDS.  Its task list: before step 0, the
+// z of its blocks 0 and 1 (and x_0 for block 0); then for each step k: the
+// chain step x_{k+1} if it owns block k + 1, then the products (s, k) of its
+// blocks s >= k + 2 (ascending), with z_s right after the product (s, s - 2).
+// A solved block is published by agent-scope atomic stores into a copy filled
+// with a sentinel before the launch, and readers poll the values themselves
 // (each written once), so a hop costs one coherent round trip and no cache
-// maintenance.  A running partial is published the same way, followed by a
-// flag holding (epoch << 12) | (chunks folded).
-constexpr int CW = 8;
+// maintenance.  Each block of L is read once per solve.
+//
+// Workgroup layout: four compute waves and one poller wave.  The poller
+// fetches each solved block the workgroup needs from the published copy
+// (polling until it is final) into a ring of kYRing LDS slots and raises the
+// slot's flag; the compute waves read it straight from the slot.  Vector loads
+// retire in order per wave, so a wave that polls drains its own loads in
+// flight: keeping the polls in their own wave leaves the compute waves' tile
+// prefetches untouched.  The compute waves load each task's 64 x 64 block
+// into a ring of register slots, four tasks ahead; every task issues the same
+// 16 loads, so the compiler's count of loads in flight stays exact and waiting
+// for one slot never waits for the ones issued after it.
 // fill value of the published copies (a signalling-NaN payload that no
 // arithmetic produces)
 constexpr unsigned long long kSentinel = 0x7FF4D5A1B2C3E4F5ull;
 
-__device__ inline unsigned int pflag_tag(unsigned int epoch, int chunks) {
-  return (epoch << 12) | (unsigned int)chunks;
-}
-
-// Thread 0 waits until *f == tag; false after a timeout (then the workgroup
-// leaves its item; the caller reports MPCHOL_HIP_ERROR).
-__device__ inline bool wait_flag(unsigned int* f, unsigned int tag, DevStatus* st) {
-  __shared__ int ok;
-  if (threadIdx.x == 0) {
-    ok = 1;
-    long spins = 0;
-    while (atomic_load_rlx(f) != tag) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > kSpinLimit) {
-        atomicOr(&st->wait_timeout, 1u);
-        ok = 0;
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  return ok != 0;
-}
-
 // Values of a published block that still hold the sentinel are polled again
 // (all of a thread's pending values in flight at once) until they are final.
-__device__ inline void settle(double (&xv)[4], const double* XP, const int64_t (&at)[4],
-                              const bool (&use)[4], DevStatus* st) {
+__device__ inline void settle_poll(double (&xv)[4], const double* XP, const int64_t (&at)[4],
+                                   const bool (&use)[4], DevStatus* st) {
   long spins = 0;
   for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      if (use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel)
+        xv[q] = coherent_load(XP + at[q]);
     bool pending = false;
 #pragma unroll
     for (int q = 0; q < 4; q++)
@@ -163,174 +204,337 @@ __device__ inline void settle(double (&xv)[4], const double* XP, const int64_t (
       for (int q = 0; q < 4; q++) xv[q] = 0.0;
       return;
     }
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-      if (use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel)
-        xv[q] = coherent_load(XP + at[q]);
   }
 }
 
-__global__ __launch_bounds__(256) void k_trsv3(int trans, const double* __restrict__ Lm,
-                                               int64_t ldl, int64_t n, int nrhs, double* X,
-                                               int64_t ldx, double* XP,
-                                               const double* __restrict__ Yd,
-                                               const int2* __restrict__ items, double* P,
-                                               unsigned int* pflag, unsigned int epoch,
-                                               DevStatus* st, int slot) {
-  __shared__ double xs[2][NB * XSW];
-  __shared__ unsigned int my_ticket;
+__device__ inline void settle(double (&xv)[4], const double* XP, const int64_t (&at)[4],
+                              const bool (&use)[4], DevStatus* st) {
+  bool pending = false;
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+    pending |= use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel;
+  if (pending) settle_poll(xv, XP, at, use, st);
+}
+
+__device__ inline int lds_load_relaxed(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Hand-off between the waves of a workgroup through LDS without a
+// workgroup-scope fence (which would also wait for the wave's global loads in
+// flight): the writer's LDS accesses are kept above the flag (compiler fence)
+// and completed (lgkmcnt 0) before it; LDS serves each wave's accesses in
+// order, so a reader that has seen the flag sees the data.
+__device__ inline void lds_settle() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), vmcnt and expcnt left alone
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ inline void lds_flag_store(int* p, int v) {
+  lds_settle();
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_flag_add(int* p, int v) {
+  lds_settle();
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Task kinds of the solve's task lists.
+enum : int { kTaskProd = 0, kTaskZ = 1, kTaskChain = 2, kTaskNone = 3 };
+
+constexpr int kYRing = 4;
+constexpr int kTrsvThreads = 320;
+
+// LDS: the y ring, two buffers for the z products, one running sum per owned
+// block ([j][r][thread]), and the ring / progress / barrier words
+constexpr int kTrsvStaticLds = (kYRing * NB * XSW + 2 * NB * XSW) * 8 + 64 * 4;
+inline size_t trsv_lds_bytes(int rows) { return (size_t)kTrsvStaticLds + (size_t)rows * 4 * 256 * 8; }
+
+__global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const double* __restrict__ Lm,
+                                                           int64_t ldl, int64_t n, int nrhs,
+                                                           double* X, int64_t ldx, double* XP,
+                                                           const double* __restrict__ Yd,
+                                                           const double* __restrict__ Md, int P,
+                                                           DevStatus* st) {
+  extern __shared__ __attribute__((aligned(16))) double trsv_pool[];
+  double* ys = trsv_pool;                         // kYRing slots of 64 x XSW
+  double* vs = ys + kYRing * NB * XSW;            // two buffers for the z products
+  int* words = reinterpret_cast<int*>(vs + 2 * NB * XSW);
+  int* ready = words;                             // [kYRing]: step + 1 of the slot's contents
+  int* progress = words + 8;                      // [4]: step each compute wave has opened
+  int* bar = words + 16;                          // z-product barrier arrivals
+  double* accs = reinterpret_cast<double*>(words + 64);
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int nblk = (int)((n + NB - 1) / NB);
-  if (tid == 0) my_ticket = atomicAdd(&st->ticket[slot], 1u);
-  __syncthreads();
-  const int2 it = items[__builtin_amdgcn_readfirstlane(my_ticket)];  // x = s (solve order), y = chunk (-1: diagonal)
-  const int sidx = __builtin_amdgcn_readfirstlane(it.x), chunk = __builtin_amdgcn_readfirstlane(it.y);
-  const bool diag = chunk < 0;
-  const int J = trans ? nblk - 1 - sidx : sidx;
-  const int64_t j0 = (int64_t)J * NB;
-  const int nj = (int)min((int64_t)NB, n - j0);
-  // output layout: lane l, register r -> row 16 w + l / 16 + 4 r, column l % 16
+  const int o = blockIdx.x;
+  const int nown = (nblk - o + P - 1) / P;
+  auto blk_of = [&](int sk) { return trans ? nblk - 1 - sk : sk; };
+  auto nk_of = [&](int sk) { return (int)min((int64_t)NB, n - (int64_t)blk_of(sk) * NB); };
+  auto row_of = [&](int j) { return o + j * P; };
+  // compute waves: output layout lane l, register r -> row 16 w + l / 16 + 4 r,
+  // column l % 16
   const int orow = 16 * w + (l >> 4), ocol = l & 15;
-
-  // the diagonal item's inverse block and right-hand side, loaded up front
-  // (both are off the chain)
-  double yv[16], bv[4];
-  if (diag) {
-    // forward x = Y v: src0 = Y (rows = output rows); backward x = Y^T v
-    tile_load(Yd + (int64_t)J * NB * NB, trans ? NB : 1, trans ? 1 : NB, trans != 0, false, NB, NB,
-              yv);
+  if (tid < kYRing) ready[tid] = 0;
+  if (tid < 4) progress[tid] = -1;
+  if (tid == 0) *bar = 0;
+  if (tid < 256)
+    for (int j = 0; j < nown; j++) {
+      // running sums start at b
+      const int64_t j0 = (int64_t)blk_of(row_of(j)) * NB;
+      const int nj = nk_of(row_of(j));
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int row = orow + 4 * r;
-      bv[r] = keep_or_zero(X[(j0 + min(row, nj - 1)) + (int64_t)min(ocol, nrhs - 1) * ldx],
-                           row < nj && ocol < nrhs);
+      for (int r = 0; r < 4; r++) {
+        const int row = orow + 4 * r;
+        accs[(j * 4 + r) * 256 + tid] =
+            keep_or_zero(X[(j0 + min(row, nj - 1)) + (int64_t)min(ocol, nrhs - 1) * ldx],
+                         row < nj && ocol < nrhs);
+      }
     }
-  }
+  __syncthreads();   // the only workgroup-wide barrier
 
-  int kb, ke;
-  if (diag) {
-    kb = max(0, CW * (sidx / CW) - CW);
-    ke = sidx;
-  } else {
-    kb = chunk * CW;
-    ke = chunk * CW + CW;
-  }
-
-  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-  // the block (J, K) of L for solve-order block sk: forward L(J, K) with K = sk
-  // (rows = output rows); backward L(K, J) with K = nblk - 1 - sk (columns =
-  // output rows)
-  auto blk_load = [&](int sk, double (&v)[16]) {
-    const int K = trans ? nblk - 1 - sk : sk;
-    const int64_t k0 = (int64_t)K * NB;
-    const int nk = (int)min((int64_t)NB, n - k0);
-    if (trans) tile_load(Lm + (k0 + j0 * ldl), (uint32_t)ldl, 1, true, false, nj, nk, v);
-    else tile_load(Lm + (j0 + k0 * ldl), 1, (uint32_t)ldl, false, false, nj, nk, v);
-  };
-  int xi, xc[4];
-  bool xu[4];
-  int64_t xat[4];
-  auto x_load = [&](int sk, double (&xv)[4]) {
-    const int K = trans ? nblk - 1 - sk : sk;
-    const int64_t k0 = (int64_t)K * NB;
-    const int nk = (int)min((int64_t)NB, n - k0);
-    xblock_coords(nk, nrhs, xc, xi, xu);
+  if (w == 4) {
+    // poller: steps 0 .. (last owned block) - 1 in order
+    const int last = row_of(nown - 1);
+    for (int k = 0; k < last; k++) {
+      const int slot = k % kYRing;
+      // the slot's previous step (k - kYRing) must be done by every compute wave
+      long spins = 0;
+      while (true) {
+        int m = lds_load_relaxed(&progress[0]);
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      xat[q] = (k0 + min(xi, nk - 1)) + (int64_t)min(xc[q], nrhs - 1) * n;
-      xv[q] = coherent_load(XP + xat[q]);
+        for (int q = 1; q < 4; q++) m = min(m, lds_load_relaxed(&progress[q]));
+        if (m > k - kYRing) {
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(&st->wait_timeout, 1u);
+          return;
+        }
+      }
+      const int64_t k0 = (int64_t)blk_of(k) * NB;
+      const int nk = nk_of(k);
+      double* dst = ys + slot * NB * XSW;
+#pragma unroll
+      for (int c0 = 0; c0 < 16; c0 += 4) {
+        double yv[4];
+        int64_t at[4];
+        bool use[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          use[q] = l < nk && c0 + q < nrhs;
+          at[q] = (k0 + min(l, nk - 1)) + (int64_t)min(c0 + q, nrhs - 1) * n;
+          yv[q] = coherent_load(XP + at[q]);
+        }
+        settle(yv, XP, at, use, st);
+#pragma unroll
+        for (int q = 0; q < 4; q++) dst[l * XSW + c0 + q] = use[q] ? yv[q] : 0.0;
+      }
+      if (l == 0) lds_flag_store(&ready[slot], k + 1);
     }
-  };
-  auto x_stage = [&](double (&xv)[4], double* dst) {
-    settle(xv, XP, xat, xu, st);
-#pragma unroll
-    for (int q = 0; q < 4; q++) dst[xi * XSW + xc[q]] = xu[q] ? xv[q] : 0.0;
-  };
-  auto nk_of = [&](int sk) {
-    const int K = trans ? nblk - 1 - sk : sk;
-    return (int)min((int64_t)NB, n - (int64_t)K * NB);
-  };
-
-  // the diagonal item's running partial of the chunks before its window: the
-  // helpers of those chunks were handed out before this item
-  double pv[4] = {0.0, 0.0, 0.0, 0.0};
-  const int hc = diag ? sidx / CW - 1 : 0;
-  if (diag && hc > 0) {
-    if (!wait_flag(&pflag[sidx], pflag_tag(epoch, hc), st)) return;
-#pragma unroll
-    for (int r = 0; r < 4; r++) pv[r] = coherent_load(P + (int64_t)sidx * NB * 16 + (orow + 4 * r) * 16 + ocol);
-  }
-
-  if (kb < ke) {
-    // tiles sk = kb .. ke - 1: the next tile's elements and solution block are
-    // in flight while this one is multiplied; the staged blocks are double
-    // buffered (one barrier per tile)
-    double va[16], vb[16], xv[4];
-    blk_load(kb, va);
-    x_load(kb, xv);
-    x_stage(xv, xs[0]);
-    __syncthreads();
-    auto step = [&](int sk, double (&cur)[16], double (&nxt)[16]) {
-      const int sn = min(sk + 1, ke - 1);     // past the end: a tile nobody uses
-      blk_load(sn, nxt);
-      x_load(sn, xv);
-      __builtin_amdgcn_sched_barrier(0);     // those loads stay ahead of the products
-      tile_mfma(cur, xs[(sk - kb) & 1], trans != 0, nk_of(sk), acc);
-      if (sk + 1 < ke) x_stage(xv, xs[(sk - kb + 1) & 1]);
-      __syncthreads();
-    };
-    int sk = kb;
-    for (; sk + 1 < ke; sk += 2) {
-      step(sk, va, vb);
-      step(sk + 1, vb, va);
-    }
-    if (sk < ke) step(sk, va, vb);
-  }
-
-  if (!diag) {
-    // fold in the running partial of the chunks before this one, publish the
-    // new partial, then the flag
-    if (chunk > 0) {
-      if (!wait_flag(&pflag[sidx], pflag_tag(epoch, chunk), st)) return;
-#pragma unroll
-      for (int r = 0; r < 4; r++)
-        acc[r] += coherent_load(P + (int64_t)sidx * NB * 16 + (orow + 4 * r) * 16 + ocol);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; r++)
-      __hip_atomic_store(reinterpret_cast<unsigned long long*>(P + (int64_t)sidx * NB * 16 +
-                                                               (orow + 4 * r) * 16 + ocol),
-                         (unsigned long long)__double_as_longlong(acc[r]), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0)
-      __hip_atomic_store(&pflag[sidx], pflag_tag(epoch, chunk + 1), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
 
-  // v = b - (window sum + running partial) into LDS; x = Y v (or Y^T v): each
-  // wave its 16 rows; publish
-#pragma unroll
-  for (int r = 0; r < 4; r++)
-    xs[0][(orow + 4 * r) * XSW + ocol] = keep_or_zero(bv[r] - (acc[r] + pv[r]), orow + 4 * r < nj);
-  __syncthreads();
-  f64x4_t xr = {0.0, 0.0, 0.0, 0.0};
-  tile_mfma(yv, xs[0], trans != 0, NB, xr);
-#pragma unroll
-  for (int r = 0; r < 4; r++) {
-    const int row = orow + 4 * r;
-    if (row < nj && ocol < nrhs) {
-      const double v = xr[r];
-      X[(j0 + row) + (int64_t)ocol * ldx] = v;
-      // the published copy, coherent across the dies without a fence
-      __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + row) + (int64_t)ocol * n),
-                         (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+  // Task list position (uniform): step k (-1: before step 0), owned block j,
+  // kind.  Step -1: z of the owned blocks 0 and 1, then x_0.  Step k >= 0: the
+  // chain step of block k + 1 if owned, then the products (s, k) of the owned
+  // s >= k + 2, each followed by z_s when s == k + 2.
+  struct Task {
+    int k, j, kind;
+  };
+  auto first_from = [&](int s) {   // smallest j with row_of(j) >= s
+    const int d = s - o;
+    return d <= 0 ? 0 : (d + P - 1) / P;
+  };
+  // first task of step k at or after owned block index j0 (kTaskNone: none)
+  auto step_first = [&](int k) -> Task {
+    if (k < 0) {
+      // z of blocks 0 and 1 (solve order), then x_0
+      const int j = first_from(0);
+      if (j < nown && row_of(j) <= 1) return Task{-1, j, kTaskZ};
+      if (o == 0) return Task{-1, 0, kTaskChain};
+      return Task{-1, 0, kTaskNone};
     }
+    if (k + 1 <= nblk - 1) {
+      const int jc = first_from(k + 1);
+      if (jc < nown && row_of(jc) == k + 1) return Task{k, jc, kTaskChain};
+    }
+    const int jp = first_from(k + 2);
+    if (jp < nown) return Task{k, jp, kTaskProd};
+    return Task{k, 0, kTaskNone};
+  };
+  auto done = [&](const Task& t) { return t.kind == kTaskNone; };
+  // the first task of the steps after k (kTaskNone: the list is done)
+  auto next_step = [&](int k) -> Task {
+    for (int kk = k + 1; kk <= nblk - 2; kk++) {
+      const Task f = step_first(kk);
+      if (f.kind != kTaskNone) return f;
+      if (first_from(kk + 1) >= nown) break;   // no owned block after kk
+    }
+    return Task{k, 0, kTaskNone};
+  };
+  auto advance = [&](Task& t) {
+    if (done(t)) return;
+    if (t.k < 0) {
+      if (t.kind == kTaskZ) {
+        const int j = t.j + 1;
+        if (j < nown && row_of(j) <= 1) { t.j = j; return; }
+        if (o == 0) { t = Task{-1, 0, kTaskChain}; return; }
+      }
+    } else if (t.kind == kTaskChain) {
+      const int jp = first_from(t.k + 2);
+      if (jp < nown) { t = Task{t.k, jp, kTaskProd}; return; }
+    } else if (t.kind == kTaskProd) {
+      if (row_of(t.j) == t.k + 2) { t.kind = kTaskZ; return; }
+      if (t.j + 1 < nown) { t.j++; return; }
+    } else {   // kTaskZ at step k >= 0 (after the product (k + 2, k))
+      if (t.j + 1 < nown) { t = Task{t.k, t.j + 1, kTaskProd}; return; }
+    }
+    t = next_step(t.k);
+  };
+
+  // the task's 64 x 64 block: a tile of L (product), the diagonal block's
+  // inverse (z), M_s (chain step), or a dummy (none, the x_0 chain step)
+  const int64_t lend = (n - 1) * ldl + n;   // end of the factor's data (elements)
+  auto issue = [&](const Task& t, double (&v)[16]) {
+    const bool prod = t.kind == kTaskProd;
+    const int sb = row_of(t.j);
+    const int J = blk_of(sb);
+    const int64_t j0 = (int64_t)J * NB;
+    const bool zk = t.kind == kTaskZ;
+    const bool ch = t.kind == kTaskChain && sb > 0;
+    const int64_t k0 = prod ? (int64_t)blk_of(t.k) * NB : 0;
+    // forward L(J, K) with K = k (rows = output rows); backward L(K, J) with
+    // K = nblk - 1 - k (columns = output rows)
+    const int64_t toff = trans ? (k0 + j0 * ldl) : (j0 + k0 * ldl);
+    const double* T = prod ? Lm + toff
+                    : zk ? Yd + (int64_t)J * NB * NB
+                    : ch ? Md + ((int64_t)trans * nblk + sb) * NB * NB
+                         : Yd;
+    const bool tt = (prod || zk) && trans;
+    const uint32_t so = prod ? (trans ? (uint32_t)ldl : 1u) : (tt ? (uint32_t)NB : 1u);
+    const uint32_t sk = prod ? (trans ? 1u : (uint32_t)ldl) : (tt ? 1u : (uint32_t)NB);
+    const uint32_t lim = prod ? (uint32_t)min((int64_t)0xFFFFFFF0ll, (lend - toff) * 8)
+                              : (uint32_t)(NB * NB * 8);
+    tile_load_b(T, so, sk, tt, lim, v);
+  };
+
+  int nz = 0;   // z products done (barrier generation)
+  // false once the list is done (or a wait timed out)
+  auto wait_y = [&](int k) -> bool {
+    if (k < 0) return true;
+    long spins = 0;
+    while (lds_load_relaxed(&ready[k % kYRing]) != k + 1) {
+      __builtin_amdgcn_s_sleep(0);
+      if (++spins > kSpinLimit) {
+        if (l == 0) atomicOr(&st->wait_timeout, 1u);
+        return false;
+      }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return true;
+  };
+  int opened = -1;   // last step opened by this wave
+  auto exec = [&](const Task& t, double (&v)[16]) -> bool {
+    if (done(t)) return false;
+    if (t.k > opened) {
+      // every task of the earlier steps is done by this wave
+      opened = t.k;
+      lds_settle();
+      if (l == 0) lds_flag_store(&progress[w], t.k);
+      if (!wait_y(t.k)) return false;
+    }
+    double* acc_j = accs + t.j * 4 * 256 + tid;
+    const double* yk = ys + (t.k >= 0 ? t.k % kYRing : 0) * NB * XSW;
+    if (t.kind == kTaskProd) {
+      f64x4_t a = {0.0, 0.0, 0.0, 0.0};
+      tile_mfma(v, yk, trans != 0, nk_of(t.k), a);
+#pragma unroll
+      for (int r = 0; r < 4; r++) acc_j[r * 256] -= a[r];
+      return true;
+    }
+    const int sb = row_of(t.j);
+    if (t.kind == kTaskZ) {
+      // z = Y r: r into LDS, the four compute waves meet, each wave its 16 rows
+      double* vb = vs + (nz & 1) * NB * XSW;
+#pragma unroll
+      for (int r = 0; r < 4; r++) vb[(orow + 4 * r) * XSW + ocol] = acc_j[r * 256];
+      nz++;
+      lds_settle();
+      if (l == 0) lds_flag_add(bar, 1);
+      long spins = 0;
+      while (lds_load_relaxed(bar) < 4 * nz) {
+        __builtin_amdgcn_s_sleep(0);
+        if (++spins > kSpinLimit) {
+          if (l == 0) atomicOr(&st->wait_timeout, 1u);
+          return false;
+        }
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      f64x4_t z = {0.0, 0.0, 0.0, 0.0};
+      tile_mfma(v, vb, trans != 0, NB, z);
+#pragma unroll
+      for (int r = 0; r < 4; r++) acc_j[r * 256] = z[r];
+      return true;
+    }
+    // chain step: x_s = z_s - M_s x_{s-1} (x_0 = z_0); publish
+    f64x4_t mx = {0.0, 0.0, 0.0, 0.0};
+    if (sb > 0) tile_mfma(v, yk, false, NB, mx);
+    const int64_t j0 = (int64_t)blk_of(sb) * NB;
+    const int nj = nk_of(sb);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = orow + 4 * r;
+      if (row < nj && ocol < nrhs) {
+        const double x = acc_j[r * 256] - mx[r];
+        X[(j0 + row) + (int64_t)ocol * ldx] = x;
+        // the published copy, coherent across the dies without a fence
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + row) + (int64_t)ocol * n),
+                           (unsigned long long)__double_as_longlong(x), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    return true;
+  };
+
+  double S0[16], S1[16], S2[16], S3[16], S4[16];
+  Task ti = step_first(-1);
+  if (done(ti)) ti = next_step(-1);
+  Task te = ti;
+  issue(ti, S0);
+  advance(ti);
+  issue(ti, S1);
+  advance(ti);
+  issue(ti, S2);
+  advance(ti);
+  issue(ti, S3);
+  advance(ti);
+  for (;;) {
+    issue(ti, S4);
+    advance(ti);
+    if (!exec(te, S0)) break;
+    advance(te);
+    issue(ti, S0);
+    advance(ti);
+    if (!exec(te, S1)) break;
+    advance(te);
+    issue(ti, S1);
+    advance(ti);
+    if (!exec(te, S2)) break;
+    advance(te);
+    issue(ti, S2);
+    advance(ti);
+    if (!exec(te, S3)) break;
+    advance(te);
+    issue(ti, S3);
+    advance(ti);
+    if (!exec(te, S4)) break;
+    advance(te);
   }
+  // no step is opened any more: release the poller's ring
+  lds_settle();
+  if (l == 0) lds_flag_store(&progress[w], 1 << 30);
 }
 
 __global__ void k_fill_sentinel(unsigned long long* p, int64_t count) {
@@ -339,47 +543,86 @@ __global__ void k_fill_sentinel(unsigned long long* p, int64_t count) {
     p[i] = kSentinel;
 }
 
-// Ticket order: the diagonal items in solve order, with the helpers of chunk
-// c handed out one chunk late, after the diagonal items of chunk c + 1.  By
-// then the solutions of chunk c are (nearly always) published, so a helper
-// rarely holds a compute unit while it waits; and D(s) of chunk m still comes
-// after the helpers of chunks <= m - 2 that it folds in.
-int trsv2_items(int64_t n, std::vector<int2>& items) {
+// M_s of the chain steps (solve order s >= 1), column-major 64 x 64 at
+// Md + ((dir nblk) + s) 4096: forward (dir 0) Y_J L(J, J - 1) with J = s;
+// backward (dir 1) Y_J^T L(J + 1, J)^T with J = nblk - 1 - s.  Elements of L
+// outside the matrix count as zero.  One workgroup per (s, dir), FP64 FMA.
+__global__ __launch_bounds__(256) void k_chain_mats(const double* __restrict__ Lm, int64_t ldl,
+                                                    int64_t n, const double* __restrict__ Yd,
+                                                    double* __restrict__ Md) {
+  __shared__ double As[64][65], Bs[64][65];
   const int nblk = (int)((n + NB - 1) / NB);
-  items.clear();
-  for (int s = 0; s < nblk; s++) {
-    items.push_back(make_int2(s, -1));
-    if ((s + 1) % CW == 0) {
-      const int c = s / CW - 1;
-      if (c >= 0)
-        for (int s2 = (c + 2) * CW; s2 < nblk; s2++) items.push_back(make_int2(s2, c));
-    }
+  const int s = blockIdx.x, dir = blockIdx.y, tid = threadIdx.x;
+  if (s == 0) return;
+  const int J = dir ? nblk - 1 - s : s;
+  const double* Y = Yd + (int64_t)J * NB * NB;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e & 63, k = e >> 6;
+    // A(i, k): Y(i, k) forward, Y(k, i) backward
+    As[i][k] = dir ? Y[k + 64 * i] : Y[i + 64 * k];
+    // B(k, c) with c = i: forward L(J 64 + k, (J - 1) 64 + c); backward
+    // L((J + 1) 64 + c, J 64 + k)
+    const int c = i;
+    const int64_t row = dir ? (int64_t)(J + 1) * NB + c : (int64_t)J * NB + k;
+    const int64_t col = dir ? (int64_t)J * NB + k : (int64_t)(J - 1) * NB + c;
+    Bs[k][c] = row < n ? Lm[row + col * ldl] : 0.0;
   }
-  return nblk;
+  __syncthreads();
+  const int i = tid & 63, c0 = (tid >> 6) * 16;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) acc[q] = 0.0;
+  for (int k = 0; k < 64; k++) {
+    const double a = As[i][k];
+#pragma unroll
+    for (int q = 0; q < 16; q++) acc[q] = fma(a, Bs[k][c0 + q], acc[q]);
+  }
+  double* M = Md + ((int64_t)dir * nblk + s) * NB * NB;
+#pragma unroll
+  for (int q = 0; q < 16; q++) M[i + 64 * (c0 + q)] = acc[q];
 }
 
-// one running 64 x 16 partial per block row
-size_t trsv2_partial_doubles(int64_t n) { return (size_t)((n + NB - 1) / NB) * NB * MAXRHS; }
-size_t trsv2_flags(int64_t n) { return (size_t)((n + NB - 1) / NB); }
-unsigned int trsv2_max_epoch() { return (1u << 20) - 1u; }
+hipError_t launch_chain_mats(const double* Lm, int64_t ldl, int64_t n, const double* Yd,
+                             double* Md, hipStream_t s) {
+  if (n <= NB) return hipSuccess;
+  const int nblk = (int)((n + NB - 1) / NB);
+  hipLaunchKernelGGL(k_chain_mats, dim3(nblk, 2), dim3(256), 0, s, Lm, ldl, n, Yd, Md);
+  return hipGetLastError();
+}
 
-hipError_t launch_trsv2(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
-                        int64_t ldx, double* XP, const double* Yd, const int2* items, int nitems, double* P,
-                        unsigned int* pflag, unsigned int epoch, DevStatus* st, int ticket_slot,
-                        hipStream_t s) {
+// Workgroups of the solve grid: every one must be resident at once (they wait
+// on each other), so at most one per compute unit, and no more than blocks.
+int trsv_grid(int64_t n, int device, int* rows_per_wg) {
+  const int nblk = (int)((n + NB - 1) / NB);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      ncu <= 0)
+    return -1;
+  const int P = std::max(1, std::min(nblk, ncu));
+  *rows_per_wg = (nblk + P - 1) / P;
+  return P;
+}
+
+size_t trsv_lds_max() { return 160 * 1024; }
+
+hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
+                       int64_t ldx, double* XP, const double* Yd, const double* Md, int P,
+                       int rows, DevStatus* st, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  if (nrhs > MAXRHS || (ticket_slot != 0 && ticket_slot != 2)) return hipErrorInvalidValue;
-  if (epoch == 0 || epoch > trsv2_max_epoch() || (n + NB - 1) / NB / CW + 1 >= 4096)
-    return hipErrorInvalidValue;
+  if (nrhs > MAXRHS || P <= 0 || (int64_t)P * rows < (n + NB - 1) / NB) return hipErrorInvalidValue;
+  const size_t lds = trsv_lds_bytes(rows);
+  if (lds > trsv_lds_max()) return hipErrorInvalidValue;
   {
     const int64_t cnt = n * nrhs;
     const unsigned gx = (unsigned)std::min<int64_t>((cnt + 255) / 256, 2048);
     hipLaunchKernelGGL(k_fill_sentinel, dim3(gx), dim3(256), 0, s,
                        reinterpret_cast<unsigned long long*>(XP), cnt);
   }
-  hipLaunchKernelGGL(k_trsv3, dim3(nitems), dim3(256), 0, s, trans, Lm, ldl, n, nrhs, X, ldx, XP, Yd,
-                     items, P, pflag, epoch, st, ticket_slot);
-  return hipGetLastError();
+  // a cooperative launch: the runtime refuses a grid that cannot be resident
+  // at once instead of letting it wait on itself
+  void* args[] = {&trans, &Lm, &ldl, &n, &nrhs, &X, &ldx, &XP, &Yd, &Md, &P, &st};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_trsv5), dim3(P),
+                                    dim3(kTrsvThreads), args, (unsigned)lds, s);
 }
 
 // R = B - A X, A symmetric with its lower triangle stored.  Workgroup I forms
@@ -417,40 +660,52 @@ __global__ __launch_bounds__(256) void k_resid3(const double* __restrict__ A, in
     const double* T = A + (tr ? q0 + i0 * lda : i0 + q0 * lda);
     tile_load(T, tr ? (uint32_t)lda : 1u, tr ? 1u : (uint32_t)lda, tr, q == I, ni, nk_of(q), v);
   };
-  int xi, xc[4];
-  bool xu[4];
   auto x_load = [&](int q, double (&xv)[4]) {
     const int64_t q0 = (int64_t)q * NB;
     const int nk = nk_of(q);
+    int xi, xc[4];
+    bool xu[4];
     xblock_coords(nk, nrhs, xc, xi, xu);
 #pragma unroll
     for (int u = 0; u < 4; u++) xv[u] = X[(q0 + min(xi, nk - 1)) + (int64_t)min(xc[u], nrhs - 1) * ldx];
   };
-  auto x_stage = [&](const double (&xv)[4], double* dst) {
+  auto x_stage = [&](int q, const double (&xv)[4], double* dst) {
+    int xi, xc[4];
+    bool xu[4];
+    xblock_coords(nk_of(q), nrhs, xc, xi, xu);
 #pragma unroll
     for (int u = 0; u < 4; u++) dst[xi * XSW + xc[u]] = keep_or_zero(xv[u], xu[u]);
   };
+  // tiles two ahead (the scheme of the block solves): the X block of a tile is
+  // loaded before the tile, so staging it never waits for the tile's loads
   f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-  double va[16], vb[16], xv[4];
-  a_load(0, va);
-  x_load(0, xv);
-  x_stage(xv, xs[0]);
+  double ta[16], tb[16], tc[16], ya[4], yb[4], yc[4];
+  x_load(0, ya);
+  a_load(0, ta);
+  if (1 < nblk) {
+    x_load(1, yb);
+    a_load(1, tb);
+  }
+  x_stage(0, ya, xs[0]);
   __syncthreads();
-  auto step = [&](int q, double (&cur)[16], double (&nxt)[16]) {
-    const int qn = min(q + 1, nblk - 1);   // past the end: a tile nobody uses
-    a_load(qn, nxt);
-    x_load(qn, xv);
+  auto step = [&](int q, double (&cur)[16], double (&x1)[4], double (&pre)[16], double (&xp)[4]) {
+    if (q + 2 < nblk) {
+      x_load(q + 2, xp);
+      a_load(q + 2, pre);
+    }
     __builtin_amdgcn_sched_barrier(0);    // those loads stay ahead of the products
     tile_mfma(cur, xs[q & 1], q > I, nk_of(q), acc);
-    x_stage(xv, xs[(q + 1) & 1]);
+    if (q + 1 < nblk) x_stage(q + 1, x1, xs[(q + 1) & 1]);
     __syncthreads();
   };
   int q = 0;
-  for (; q + 1 < nblk; q += 2) {
-    step(q, va, vb);
-    step(q + 1, vb, va);
+  for (; q + 2 < nblk; q += 3) {
+    step(q, ta, yb, tc, yc);
+    step(q + 1, tb, yc, ta, ya);
+    step(q + 2, tc, ya, tb, yb);
   }
-  if (q < nblk) step(q, va, vb);
+  if (q < nblk) step(q, ta, yb, tc, yc);
+  if (q + 1 < nblk) step(q + 1, tb, yc, ta, ya);
 #pragma unroll
   for (int r = 0; r < 4; r++) {
     const int row = orow + 4 * r;
