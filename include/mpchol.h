@@ -152,6 +152,31 @@ int mpchol_solve(mpchol_ctx ctx, int64_t n, int64_t nrhs, const double* A, int64
                  void* stream, mpchol_info* info);
 
 /*
+ * mpchol_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve and refinement, run on the same kernels, with every scratch
+ * buffer in a fixed device array that the library owns (one per GPU, held
+ * until the process ends; about 29 MB: MPCHOL_NOALLOC_MAX_N x
+ * MPCHOL_NOALLOC_MAX_RHS).  No context, no hipMalloc / hipFree / host pinning,
+ * no allocating library call; the first call on a device only looks up the
+ * array's address there.
+ *   device      the GPU (made current; stream must belong to it).
+ *   The other arguments and the result are those of mpchol_solve; info's
+ *   ms_solve is host wall-clock time of the call.
+ * Every call on one GPU uses that GPU's array, so calls that overlap on one
+ * GPU (other host threads, other streams) race: serialize them.  Each call
+ * clears or overwrites everything it reads from the array.
+ * Errors: -1 device < 0; -2 n < 0 or n > MPCHOL_NOALLOC_MAX_N; -3 nrhs < 0 or
+ * nrhs > MPCHOL_NOALLOC_MAX_RHS; then as mpchol_solve.
+ */
+#define MPCHOL_NOALLOC_MAX_N 16384
+#define MPCHOL_NOALLOC_MAX_RHS 16
+int mpchol_solve_noalloc(int device, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                         const double* L, int64_t ldl, const double* B, int64_t ldb,
+                         double* X, int64_t ldx, double tol, int32_t max_iter,
+                         void* stream, mpchol_info* info);
+
+/*
  * Factor and solve `batch` independent SPD systems of uneven sizes with ONE
  * persistent kernel launch (captured once into a hipGraph and replayed while
  * the arguments stay the same): one workgroup per compute unit pulls systems

@@ -692,32 +692,51 @@ static int ensure_trsv(mpchol_ctx c, int64_t n) {
   return 0;
 }
 
-// X <- L^-T L^-1 X for up to kMaxRhs columns at a time (c->tsv_yd holds the
-// diagonal-block inverses of L).
-static int chol_solve_inplace(mpchol_ctx c, int64_t n, int64_t nrhs, const double* L,
+// Device and host buffers of one solve call: the context's (grown on demand)
+// or the allocation-free entry point's fixed scratch.
+struct SolveBufs {
+  int device;
+  DevStatus* dst;      // device status words
+  DevStatus* hst;      // host copy
+  double* yd;          // diagonal-block inverses (nblk 4096), then the chain-step
+  double* md;          //   matrices (2 nblk 4096)
+  double* xp;          // published solution blocks (n kMaxRhs)
+  double* rbuf;        // residual / correction (n nrhs)
+  double* npart;       // norm partials (kNormParts kMaxRhs 2), device
+  double* hnpart;      //   and host
+  mpchol_ctx prof;     // launch timing (NULL: none)
+};
+
+static int sb_prof_begin(const SolveBufs& B, int kind, double work, hipStream_t s) {
+  return B.prof && B.prof->prof_mask ? prof_begin(B.prof, kind, work, s) : -1;
+}
+static void sb_prof_end(const SolveBufs& B, int i, hipStream_t s) {
+  if (B.prof) prof_end(B.prof, i, s);
+}
+
+// X <- L^-T L^-1 X for up to kMaxRhs columns at a time (B.yd / B.md hold the
+// diagonal-block inverses and chain-step matrices of L).
+static int chol_solve_inplace(const SolveBufs& B, int64_t n, int64_t nrhs, const double* L,
                               int64_t ldl, double* X, int64_t ldx, hipStream_t s) {
   const double lbytes = (double)n * (n + 1) / 2 * 8.0;
-  int r = ensure_trsv(c, n);
-  if (r) return r;
   int rows = 0;
-  const int P = trsv_grid(n, c->device, &rows);
+  const int P = trsv_grid(n, B.device, &rows);
   if (P <= 0) return MPCHOL_HIP_ERROR;
   for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
     for (int trans = 0; trans < 2; trans++) {
-      const int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRSV, lbytes, s) : -1;
-      HIPCHK(launch_trsv(trans, L, ldl, n, nc, X + c0 * ldx, ldx, c->tsv_x, c->tsv_yd,
-                         c->tsv_yd + (size_t)((n + 63) / 64) * 4096, P, rows, c->dst, s));
-      prof_end(c, pk, s);
+      const int pk = sb_prof_begin(B, MPCHOL_PROF_TRSV, lbytes, s);
+      HIPCHK(launch_trsv(trans, L, ldl, n, nc, X + c0 * ldx, ldx, B.xp, B.yd, B.md, P, rows, B.dst,
+                         s));
+      sb_prof_end(B, pk, s);
     }
   }
   return 0;
 }
 
-int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t lda,
-                 const double* L, int64_t ldl, const double* B, int64_t ldb, double* X,
-                 int64_t ldx, double tol, int32_t max_iter, void* stream, mpchol_info* info) {
-  if (!c) return -1;
+static int solve_args(int64_t n, int64_t nrhs, const double* A, int64_t lda, const double* L,
+                      int64_t ldl, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                      int32_t max_iter) {
   if (n < 0) return -2;
   if (nrhs < 0) return -3;
   if (A && lda < std::max<int64_t>(1, n)) return -5;
@@ -728,66 +747,58 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
   if (!X && n > 0 && nrhs > 0) return -10;
   if (ldx < std::max<int64_t>(1, n)) return -11;
   if (max_iter < 0) return -13;
-  if (info) std::memset(info, 0, sizeof(*info));
-  if (n == 0 || nrhs == 0) return 0;
-  hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->device));
-  HIPCHK(hipEventRecord(c->ev0, s));
-  HIPCHK(launch_status_init(c->dst, s));
+  return 0;
+}
+
+// The solve and its refinement on the stream, with the buffers in Bf; returns
+// the status (info filled except ms_solve).
+static int solve_run(const SolveBufs& Bf, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                     const double* L, int64_t ldl, const double* B, int64_t ldb, double* X,
+                     int64_t ldx, double tol, int32_t max_iter, hipStream_t s, mpchol_info* info) {
+  HIPCHK(launch_status_init(Bf.dst, s));
   HIPCHK(launch_copy_cols(n, (int)nrhs, B, ldb, X, ldx, s));
   {
-    int r0 = ensure_trsv(c, n);
-    if (r0) return r0;
     // used by every triangular solve of this call
-    const int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_TRINV,
-                                             (double)((n + 63) / 64) * 64.0 * 64.0 * 64.0 / 3.0, s)
-                                : -1;
-    HIPCHK(launch_diag_inv(L, ldl, n, c->tsv_yd, s));
-    HIPCHK(launch_chain_mats(L, ldl, n, c->tsv_yd, c->tsv_yd + (size_t)((n + 63) / 64) * 4096, s));
-    prof_end(c, pk, s);
+    const int pk = sb_prof_begin(Bf, MPCHOL_PROF_TRINV,
+                                 (double)((n + 63) / 64) * 64.0 * 64.0 * 64.0 / 3.0, s);
+    HIPCHK(launch_diag_inv(L, ldl, n, Bf.yd, s));
+    HIPCHK(launch_chain_mats(L, ldl, n, Bf.yd, Bf.md, s));
+    sb_prof_end(Bf, pk, s);
   }
-  int r = chol_solve_inplace(c, n, nrhs, L, ldl, X, ldx, s);
+  int r = chol_solve_inplace(Bf, n, nrhs, L, ldl, X, ldx, s);
   if (r) return r;
   int status = MPCHOL_OK;
   int iters = 0;
   double corr = 0.0;
   if (A && max_iter > 0) {
-    if (c->rbuf_count < n * nrhs) {
-      HIPCHK(hipStreamSynchronize(s));
-      if (c->rbuf) HIPCHK(hipFree(c->rbuf));
-      c->rbuf = nullptr;
-      HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
-      c->rbuf_count = n * nrhs;
-    }
-    double* R = c->rbuf;
+    double* R = Bf.rbuf;
     double prev = INFINITY;
     int grew = 0;
     status = MPCHOL_NOT_CONVERGED;
     for (int it = 1; it <= max_iter; it++) {
       for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
         int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
-        int pk = c->prof_mask ? prof_begin(c, MPCHOL_PROF_RESIDUAL,
-                                           (double)n * (n + 1) / 2 * 8.0, s) : -1;
+        int pk = sb_prof_begin(Bf, MPCHOL_PROF_RESIDUAL, (double)n * (n + 1) / 2 * 8.0, s);
         HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
                                s));
-        prof_end(c, pk, s);
+        sb_prof_end(Bf, pk, s);
       }
-      r = chol_solve_inplace(c, n, nrhs, L, ldl, R, n, s);
+      r = chol_solve_inplace(Bf, n, nrhs, L, ldl, R, n, s);
       if (r) return r;
       double worst = 0.0;
       bool bad = false;
       for (int64_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
         int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
-        HIPCHK(launch_update_norms(n, nc, X + c0 * ldx, ldx, R + c0 * n, n, c->npart, kNormParts,
+        HIPCHK(launch_update_norms(n, nc, X + c0 * ldx, ldx, R + c0 * n, n, Bf.npart, kNormParts,
                                    nullptr, s));
-        HIPCHK(hipMemcpyAsync(c->hnpart, c->npart, sizeof(double) * kNormParts * nc * 2,
+        HIPCHK(hipMemcpyAsync(Bf.hnpart, Bf.npart, sizeof(double) * kNormParts * nc * 2,
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int cc = 0; cc < nc; cc++) {
           double dm = 0.0, xm = 0.0;
           for (int w = 0; w < kNormParts; w++) {
-            dm = std::max(dm, c->hnpart[(w * nc + cc) * 2 + 0]);
-            xm = std::max(xm, c->hnpart[(w * nc + cc) * 2 + 1]);
+            dm = std::max(dm, Bf.hnpart[(w * nc + cc) * 2 + 0]);
+            xm = std::max(xm, Bf.hnpart[(w * nc + cc) * 2 + 1]);
           }
           if (!std::isfinite(dm) || !std::isfinite(xm)) bad = true;
           double rr = xm > 0.0 ? dm / xm : dm;
@@ -812,18 +823,76 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
       prev = worst;
     }
   }
-  HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipMemcpyAsync(Bf.hst, Bf.dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (c->hst->wait_timeout) status = MPCHOL_HIP_ERROR;
+  if (Bf.hst->wait_timeout) status = MPCHOL_HIP_ERROR;
   if (info) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    info->ms_solve = ms;
     info->status = status;
     info->ir_iters = iters;
     info->final_rel_corr = corr;
   }
+  return status;
+}
+
+int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                 const double* L, int64_t ldl, const double* B, int64_t ldb, double* X,
+                 int64_t ldx, double tol, int32_t max_iter, void* stream, mpchol_info* info) {
+  if (!c) return -1;
+  const int bad = solve_args(n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, max_iter);
+  if (bad) return bad;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipEventRecord(c->ev0, s));
+  int r = ensure_trsv(c, n);
+  if (r) return r;
+  if (A && max_iter > 0 && c->rbuf_count < n * nrhs) {
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->rbuf) HIPCHK(hipFree(c->rbuf));
+    c->rbuf = nullptr;
+    HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
+    c->rbuf_count = n * nrhs;
+  }
+  const SolveBufs Bf{c->device, c->dst, c->hst, c->tsv_yd,
+                     c->tsv_yd + (size_t)((n + 63) / 64) * 4096, c->tsv_x, c->rbuf, c->npart,
+                     c->hnpart, c};
+  const int status = solve_run(Bf, n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, tol, max_iter, s, info);
+  if (status == MPCHOL_HIP_ERROR || status < 0) return status;
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    info->ms_solve = ms;
+  }
+  return status;
+}
+
+int mpchol_solve_noalloc(int device, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                         const double* L, int64_t ldl, const double* B, int64_t ldb, double* X,
+                         int64_t ldx, double tol, int32_t max_iter, void* stream,
+                         mpchol_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (device < 0) return -1;
+  const int bad = solve_args(n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, max_iter);
+  if (bad) return bad;
+  if (n > MPCHOL_NOALLOC_MAX_N) return -2;
+  if (nrhs > MPCHOL_NOALLOC_MAX_RHS) return -3;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(device));
+  NoAllocScratch sc;
+  if (noalloc_scratch(device, &sc) != hipSuccess) return MPCHOL_HIP_ERROR;
+  DevStatus hst;
+  double hnpart[kNormParts * kMaxRhs * 2];
+  const SolveBufs Bf{device, sc.status, &hst, sc.yd, sc.yd + (size_t)((n + 63) / 64) * 4096, sc.xp,
+                     sc.rbuf, sc.npart, hnpart, nullptr};
+  const int status = solve_run(Bf, n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, tol, max_iter, s, info);
+  if (info)
+    info->ms_solve = (float)std::chrono::duration<double, std::milli>(
+                         std::chrono::steady_clock::now() - t0).count();
   return status;
 }
 

@@ -129,6 +129,19 @@ hipError_t launch_chain_mats(const double* Lm, int64_t ldl, int64_t n, const dou
 hipError_t launch_trsv(int trans, const double* Lm, int64_t ldl, int64_t n, int nrhs, double* X,
                        int64_t ldx, double* XP, const double* Yd, const double* Md, int P,
                        int rows, DevStatus* st, hipStream_t s);
+// Fixed scratch of the allocation-free solve (one array per GPU, the device
+// address looked up once per device): status words, diagonal-block inverses
+// and chain-step matrices, published blocks, residual, norm partials, sized
+// for n <= MPCHOL_NOALLOC_MAX_N and 16 right-hand sides.  The caller has made
+// `device` current.
+struct NoAllocScratch {
+  DevStatus* status;
+  double* yd;      // 3 nblk 4096 doubles
+  double* xp;      // n 16
+  double* rbuf;    // n 16
+  double* npart;   // 64 16 2
+};
+hipError_t noalloc_scratch(int device, NoAllocScratch* out);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
                            hipStream_t s);

@@ -6,7 +6,10 @@
 //     triangle read;
 //   - X += D with per-column max-abs of D and X for the stopping rule.
 #include <algorithm>
+#include <mutex>
 #include <vector>
+
+#include "../../include/mpchol.h"
 
 #include "internal.h"
 
@@ -588,6 +591,46 @@ hipError_t launch_chain_mats(const double* Lm, int64_t ldl, int64_t n, const dou
   const int nblk = (int)((n + NB - 1) / NB);
   hipLaunchKernelGGL(k_chain_mats, dim3(nblk, 2), dim3(256), 0, s, Lm, ldl, n, Yd, Md);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Scratch of the allocation-free solve.  A file-scope device array: each GPU
+// holds its own copy at its own address, which host code looks up once per
+// device (the array's name is not a device address in host code).
+constexpr int64_t kNaBlocks = (MPCHOL_NOALLOC_MAX_N + NB - 1) / NB;
+constexpr size_t kNaStatus = 32;   // doubles reserved for DevStatus
+constexpr size_t kNaYd = (size_t)3 * kNaBlocks * NB * NB;
+constexpr size_t kNaVec = (size_t)MPCHOL_NOALLOC_MAX_N * MPCHOL_NOALLOC_MAX_RHS;
+constexpr size_t kNaParts = 64 * 16 * 2;
+constexpr size_t kNaDoubles = kNaStatus + kNaYd + 2 * kNaVec + kNaParts;
+static_assert(sizeof(DevStatus) <= kNaStatus * sizeof(double), "status words fit");
+static_assert(MPCHOL_NOALLOC_MAX_RHS <= MAXRHS, "one solve launch per call");
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+hipError_t noalloc_scratch(int device, NoAllocScratch* out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (!ptr[device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      if (!p) return hipErrorInvalidSymbol;
+      ptr[device] = static_cast<double*>(p);
+    }
+    base = ptr[device];
+  }
+  out->status = reinterpret_cast<DevStatus*>(base);
+  out->yd = base + kNaStatus;
+  out->xp = out->yd + kNaYd;
+  out->rbuf = out->xp + kNaVec;
+  out->npart = out->rbuf + kNaVec;
+  return hipSuccess;
 }
 
 // Workgroups of the solve grid: every one must be resident at once (they wait

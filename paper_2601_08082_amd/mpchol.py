@@ -85,6 +85,8 @@ def _load() -> ct.CDLL:
                                   ct.POINTER(CInfo)]
     lib.mpchol_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, dbl, i32, vp,
                                  ct.POINTER(CInfo)]
+    lib.mpchol_solve_noalloc.argtypes = [ct.c_int, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                         dbl, i32, vp, ct.POINTER(CInfo)]
     lib.mpchol_factor_batched.argtypes = [vp, i64, ct.POINTER(i64), ct.POINTER(vp),
                                           ct.POINTER(i64), ct.POINTER(vp), ct.POINTER(i64), i64,
                                           ct.POINTER(vp), ct.POINTER(vp), dbl, i32,
@@ -411,6 +413,38 @@ class Context:
 
 MLP_IN, MLP_H, MLP_OUT = 5, 64, 4
 MLP_PARAMS = 4814
+
+
+NOALLOC_MAX_N = 16384
+NOALLOC_MAX_RHS = 16
+
+
+def solve_noalloc(L_cm, B_cm, n: int, A_cm=None, tol: float = 1e-13, max_iter: int = 20,
+                  X_cm=None, device: int = 0, stream=None):
+    """mpchol_solve_noalloc: the solve + refinement of Context.solve on the
+    library's fixed per-GPU scratch (n <= NOALLOC_MAX_N, nrhs <=
+    NOALLOC_MAX_RHS); returns (X_cm, info dict).  X_cm must be given by a
+    caller that cannot allocate."""
+    import torch
+    _check_cm(L_cm, "L")
+    _check_cm(B_cm, "B")
+    if A_cm is not None:
+        _check_cm(A_cm, "A")
+    nrhs = B_cm.shape[0]
+    if X_cm is None:
+        X_cm = torch.zeros_like(B_cm)
+    _check_cm(X_cm, "X")
+    info = CInfo()
+    r = lib.mpchol_solve_noalloc(device, n, nrhs, _ptr(A_cm),
+                                 A_cm.shape[1] if A_cm is not None else max(1, n),
+                                 _ptr(L_cm), L_cm.shape[1], _ptr(B_cm), B_cm.shape[1],
+                                 _ptr(X_cm), X_cm.shape[1], tol, max_iter,
+                                 _stream_handle(stream), ct.byref(info))
+    if r < 0:
+        raise ValueError(f"mpchol_solve_noalloc: invalid argument {-r}")
+    if r == HIP_ERROR:
+        raise RuntimeError("mpchol_solve_noalloc: HIP error")
+    return X_cm, info.as_dict()
 
 
 def _raise(r: int, name: str):
