@@ -63,6 +63,10 @@ def _load():
     lib.orc_split.restype = i64
     lib.orc_factor.argtypes = [i64, dp, i64, ct.POINTER(_Tree), ct.POINTER(i64)]
     lib.orc_factor.restype = ct.c_int32
+    lib.orc_tree_trsm.argtypes = [i64, i64, dp, i64, ct.POINTER(_Tree)]
+    lib.orc_tree_trsm.restype = ct.c_int32
+    lib.orc_tree_syrk.argtypes = [i64, i64, dp, i64, ct.POINTER(_Tree)]
+    lib.orc_tree_syrk.restype = ct.c_int32
     lib.orc_potrf_unblocked.argtypes = [i64, dp, i64, ct.POINTER(i64)]
     lib.orc_potrf_unblocked.restype = ct.c_int32
     lib.orc_trsm_left_lower.argtypes = [i64, i64, dp, i64, dp, i64]
@@ -170,6 +174,27 @@ def factor(A: np.ndarray, n: Optional[int] = None, tree: Optional[Tree] = None):
     ts = tree.c_struct()
     st = lib.orc_factor(n, _dp(L), _ld(L), ct.byref(ts), ct.byref(fi))
     return L, int(st), int(fi.value)
+
+
+def tree_trsm(A: np.ndarray, m: int, k: int, tree: Optional[Tree] = None):
+    """Tree-TRSM on its own (Algorithm 2, the precision list read by its own
+    recursion depth): A[k:k+m, :k] <- A[k:k+m, :k] L^{-T} with L the lower
+    triangle of A[:k, :k].  Returns (new array, status)."""
+    tree = Tree() if tree is None else tree
+    M = np.array(A, dtype=np.float64, order="F", copy=True)
+    ts = tree.c_struct()
+    st = _load().orc_tree_trsm(m, k, _dp(M), _ld(M), ct.byref(ts))
+    return M, int(st)
+
+
+def tree_syrk(A: np.ndarray, n: int, k: int, tree: Optional[Tree] = None):
+    """Tree-SYRK on its own (Algorithm 3): the lower triangle of A[k:k+n, k:k+n]
+    <- itself - A[k:k+n, :k] A[k:k+n, :k]^T.  Returns (new array, status)."""
+    tree = Tree() if tree is None else tree
+    M = np.array(A, dtype=np.float64, order="F", copy=True)
+    ts = tree.c_struct()
+    st = _load().orc_tree_syrk(n, k, _dp(M), _ld(M), ct.byref(ts))
+    return M, int(st)
 
 
 def potrf_unblocked(A: np.ndarray, n: Optional[int] = None):

@@ -354,6 +354,70 @@ int32_t orc_factor(int64_t n, double* A, int64_t lda, const orc_tree* t,
   return ORC_OK;
 }
 
+/* ------------------------------------------- Tree-TRSM / Tree-SYRK alone */
+
+/* Precision of the updates issued at depth d of a Tree-TRSM / Tree-SYRK run
+ * on its own: the precision list read from the outermost recursion level
+ * (Section 4.2), deeper levels repeating the last entry. */
+static int32_t level_precision(const orc_tree* t, int depth) {
+  return t->offdiag[depth < t->nlevels - 1 ? depth : t->nlevels - 1];
+}
+
+/* Algorithm 2 with the GEMM of depth d in level_precision(d). */
+static void rec_trsm_depth(ctx_t* c, int64_t r0, int64_t m, int64_t c0, int64_t k, int depth) {
+  if (m <= 0 || k <= 0) return;
+  if ((m < k ? m : k) <= c->t->leaf) {
+    leaf_trsm(c, r0, m, c0, k);
+    return;
+  }
+  int64_t k1 = orc_split(k, c->t->split_align);
+  rec_trsm_depth(c, r0, m, c0, k1, depth + 1);
+  /* B2 -= B1 L21^T */
+  gemm_q(c, r0, c0 + k1, m, k - k1, r0, c0, c0 + k1, c0, k1, level_precision(c->t, depth), 0);
+  rec_trsm_depth(c, r0, m, c0 + k1, k - k1, depth + 1);
+}
+
+/* Algorithm 3 (alpha = -1, beta = 1) with the GEMM of depth d, and a leaf
+ * SYRK reached at depth d, in level_precision(d) (the leaf SYRK in leaf_prec
+ * when syrk_leaf_mode = 1). */
+static void rec_syrk_depth(ctx_t* c, int64_t c0, int64_t s, int64_t p0, int64_t k, int depth) {
+  if (s <= 0 || k <= 0) return;
+  if (s <= c->t->leaf) {
+    int32_t p = c->t->syrk_leaf_mode ? c->t->leaf_prec : level_precision(c->t, depth);
+    gemm_q(c, c0, c0, s, s, c0, p0, c0, p0, k, p, 1);
+    return;
+  }
+  int64_t s1 = orc_split(s, c->t->split_align);
+  rec_syrk_depth(c, c0, s1, p0, k, depth + 1);
+  /* C21 -= P2 P1^T */
+  gemm_q(c, c0 + s1, c0, s - s1, s1, c0 + s1, p0, c0, p0, k, level_precision(c->t, depth), 0);
+  rec_syrk_depth(c, c0 + s1, s - s1, p0, k, depth + 1);
+}
+
+int32_t orc_tree_trsm(int64_t m, int64_t k, double* A, int64_t lda, const orc_tree* t) {
+  ctx_t c;
+  c.A = A;
+  c.lda = lda;
+  c.t = t;
+  c.failed = 0;
+  c.nonfinite = 0;
+  c.next_node = 0;
+  rec_trsm_depth(&c, k, m, 0, k, 0);
+  return c.nonfinite ? ORC_NONFINITE : ORC_OK;
+}
+
+int32_t orc_tree_syrk(int64_t n, int64_t k, double* A, int64_t lda, const orc_tree* t) {
+  ctx_t c;
+  c.A = A;
+  c.lda = lda;
+  c.t = t;
+  c.failed = 0;
+  c.nonfinite = 0;
+  c.next_node = 0;
+  rec_syrk_depth(&c, k, n, 0, k, 0);
+  return c.nonfinite ? ORC_NONFINITE : ORC_OK;
+}
+
 static int64_t count_nodes(int64_t m, int32_t leaf, int32_t align) {
   if (m <= leaf) return 0;
   int64_t m1 = orc_split(m, align);

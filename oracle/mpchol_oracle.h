@@ -52,6 +52,19 @@ int64_t orc_split(int64_t m, int32_t align);
 int32_t orc_factor(int64_t n, double* A, int64_t lda, const orc_tree* t,
                    int64_t* failed_index);
 
+/* Tree-TRSM (Algorithm 2) and Tree-SYRK (Algorithm 3) on their own, the
+ * sub-kernels timed separately in Section 4.2, on blocks of one matrix as
+ * Algorithm 1 calls them:
+ *   orc_tree_trsm: A21 = A[k:k+m, 0:k] <- A21 L11^{-T}, L11 = lower A[0:k, 0:k];
+ *   orc_tree_syrk: lower A22 = A[k:k+n, k:k+n] <- A22 - A21 A21^T,
+ *                  A21 = A[k:k+n, 0:k].
+ * The precision list is read by the depth of this recursion: the GEMM issued
+ * at depth d runs in offdiag[min(d, nlevels-1)], and so does a leaf SYRK
+ * reached at depth d (leaf_prec when syrk_leaf_mode = 1); leaf TRSMs run in
+ * leaf_prec.  node_prec is not used.  Returns ORC_OK or ORC_NONFINITE. */
+int32_t orc_tree_trsm(int64_t m, int64_t k, double* A, int64_t lda, const orc_tree* t);
+int32_t orc_tree_syrk(int64_t n, int64_t k, double* A, int64_t lda, const orc_tree* t);
+
 /* Unblocked Cholesky-Banachiewicz (FP64), the textbook definition. */
 int32_t orc_potrf_unblocked(int64_t n, double* A, int64_t lda, int64_t* failed_index);
 

@@ -184,3 +184,91 @@ def factor_lca(A: np.ndarray, n: int, leaf: int, offdiag: Sequence[int],
                 else:
                     M[ii, jj] = M[ii, jj] - upd
     return np.tril(M)
+
+
+# --------------------------------------------------------------------------
+# Tree-TRSM and Tree-SYRK on their own, as tile loops over the leaf blocks of
+# their own recursion tree (the precision list read by that tree's depth).
+#
+# Tree-TRSM splits only L's order k.  Column block j of B receives, from each
+# ancestor node N of leaf j that holds j in its second half, one GEMM over all
+# the column blocks of N's first half (the GEMM Algorithm 2 issues at N), in
+# the precision of N's depth, outermost ancestor first; then the leaf solve.
+# Tree-SYRK splits only C's order n.  Tile (I, J), I > J, of C receives one
+# product P_I P_J^T from the GEMM issued at LCA(I, J); a diagonal tile from the
+# leaf SYRK reached at its leaf's depth.  Equal to the recursions when every
+# block scale is 1, up to the FP64 summation order inside a product.
+
+def _leaf_of(leaves: List[Node], pos: int) -> int:
+    for i, lf in enumerate(leaves):
+        if lf.start <= pos < lf.start + lf.size:
+            return i
+    raise ValueError(pos)
+
+
+def _product(X: np.ndarray, Y: np.ndarray, p: int) -> np.ndarray:
+    """X Y^T in precision p (operands rounded, accumulation as in the header)."""
+    if p == F64:
+        return X @ Y.T
+    Xq, Yq = _q(X, p), _q(Y, p)
+    return _acc32(Xq[:, None, :] * Yq[None, :, :], p)
+
+
+def trsm_lca(A: np.ndarray, m: int, k: int, leaf: int, offdiag: Sequence[int],
+             leaf_prec: int = F64, align: int = 1) -> np.ndarray:
+    """Returns B = A[k:k+m, :k] L^{-T} (L = lower A[:k, :k]) by the tile loop.
+    Requires m > leaf (the recursion then splits k down to leaf-sized blocks)."""
+    root, leaves = build_tree(k, leaf, align)
+    L = np.tril(np.array(A[:k, :k], dtype=np.float64))
+    B = np.array(A[k:k + m, :k], dtype=np.float64)
+    lp32 = leaf_prec == F32
+    for lf in leaves:
+        jj = slice(lf.start, lf.start + lf.size)
+        # ancestors of this leaf, outermost first, that hold it in their second half
+        nd = root
+        while nd.left is not None:
+            mid = nd.left.start + nd.left.size
+            if lf.start >= mid:
+                p = offdiag[min(nd.depth, len(offdiag) - 1)]
+                ll = slice(nd.left.start, mid)
+                B[:, jj] = B[:, jj] - _product(B[:, ll], L[jj, ll], p)
+                nd = nd.right
+            else:
+                nd = nd.left
+        # leaf solve, column by column
+        Lk = L[jj, jj]
+        Bt = B[:, jj].copy()
+        for j in range(lf.size):
+            if lp32:
+                col = Bt[:, j].astype(np.float32)
+                for q in range(j):
+                    col = (col - Bt[:, q].astype(np.float32) * np.float32(Lk[j, q])).astype(np.float32)
+                Bt[:, j] = (col / np.float32(Lk[j, j])).astype(np.float64)
+            else:
+                col = Bt[:, j].copy()
+                for q in range(j):
+                    col = col - Bt[:, q] * Lk[j, q]
+                Bt[:, j] = col / Lk[j, j]
+        B[:, jj] = Bt
+    return B
+
+
+def syrk_lca(A: np.ndarray, n: int, k: int, leaf: int, offdiag: Sequence[int],
+             leaf_prec: int = F64, align: int = 1, syrk_leaf_mode: int = 0) -> np.ndarray:
+    """Returns the lower triangle of A[k:k+n, k:k+n] - P P^T, P = A[k:k+n, :k],
+    by the tile loop (strictly upper triangle zero)."""
+    root, leaves = build_tree(n, leaf, align)
+    C = np.array(A[k:k + n, k:k + n], dtype=np.float64)
+    P = np.array(A[k:k + n, :k], dtype=np.float64)
+    for I, li in enumerate(leaves):
+        ii = slice(li.start, li.start + li.size)
+        for J in range(I + 1):
+            lj = leaves[J]
+            jj = slice(lj.start, lj.start + lj.size)
+            if I == J:
+                p = leaf_prec if syrk_leaf_mode else offdiag[min(li.depth, len(offdiag) - 1)]
+                C[ii, jj] = C[ii, jj] - np.tril(_product(P[ii], P[jj], p))
+            else:
+                nd = _lca(root, li.start, lj.start)
+                C[ii, jj] = C[ii, jj] - _product(P[ii], P[jj], offdiag[min(nd.depth, len(offdiag) - 1)])
+    return np.tril(C)
