@@ -133,6 +133,30 @@ int mpchol_factor(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
                   void* stream, mpchol_info* info);
 
 /*
+ * Tree-TRSM (Algorithm 2) and Tree-SYRK (Algorithm 3) on their own -- the
+ * sub-kernels the paper times separately (Section 4.2) -- on blocks of one
+ * matrix A (column-major, lda >= a + k), exactly as Algorithm 1 calls them:
+ *   mpchol_trsm: A21 = A(k:k+m, 0:k) <- A21 L11^-T, L11 the lower triangle
+ *                of A(0:k, 0:k) (a Cholesky factor; not modified);
+ *   mpchol_syrk: the lower triangle of A22 = A(k:k+n, k:k+n)
+ *                <- A22 - A21 A21^T with A21 = A(k:k+n, 0:k) (not modified).
+ * The precision list is read by the depth of their own recursion (Section
+ * 4.2's lists run from the outermost level inward): the GEMM issued at depth
+ * d, and a leaf SYRK reached at depth d, run in offdiag[min(d, nlevels-1)]
+ * (a leaf SYRK in leaf_prec when syrk_leaf_mode = 1); leaf TRSMs run in
+ * leaf_prec (FP64 ones through inverses of L11's leaf blocks formed first,
+ * unless leaf_trsm = 1).  node_prec must be empty.
+ *   info   NULL: the call only enqueues.  Otherwise the stream is synchronized
+ *          and info receives status and ms_factor (the time of the update).
+ * Errors: -1 ctx NULL; -2 m (n) < 0; -3 k < 0; -4 A NULL; -5 lda < m + k
+ * (n + k); -6 bad descriptor.
+ */
+int mpchol_trsm(mpchol_ctx ctx, int64_t m, int64_t k, double* A, int64_t lda,
+                const mpchol_tree* tree, void* stream, mpchol_info* info);
+int mpchol_syrk(mpchol_ctx ctx, int64_t n, int64_t k, double* A, int64_t lda,
+                const mpchol_tree* tree, void* stream, mpchol_info* info);
+
+/*
  * Solve A X = B with the factor L, then refine with FP64 residuals (the
  * paper's abstract names the symmetric linear solve; the refinement is the
  * classic mixed-precision iterative refinement its related work surveys,

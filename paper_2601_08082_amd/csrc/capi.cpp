@@ -213,15 +213,21 @@ static int ensure_ws(mpchol_ctx c, size_t bytes, int64_t parts) {
   return 0;
 }
 
-static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, Plan** out) {
+// op 0: Tree-POTRF of order n; 1: Tree-TRSM of an n x k block against a k x k
+// factor; 2: Tree-SYRK of order n with k columns.
+static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, Plan** out,
+                    int op = 0, int64_t k = 0) {
   std::string key = plan_key(n, ldl, t);
+  if (op) key = (op == 1 ? "trsm:" : "syrk:") + std::to_string(k) + ":" + key;
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = it->second.get();
     return 0;
   }
   std::unique_ptr<Plan> P(new Plan());
-  build_plan(*P, n, ldl, t);
+  if (op == 1) build_trsm_plan(*P, n, k, ldl, t);
+  else if (op == 2) build_syrk_plan(*P, n, k, ldl, t);
+  else build_plan(*P, n, ldl, t);
   if (upload(&P->d_maxabs, P->maxabs) || upload(&P->d_casts, P->casts) ||
       upload(&P->d_gemms, P->gemms)) {
     free_plan(*P);
@@ -667,6 +673,58 @@ int mpchol_factor(mpchol_ctx c, int64_t n, const double* A, int64_t lda, double*
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   info->ms_factor = ms;
   return status_from(*c->hst, info);
+}
+
+// Tree-TRSM / Tree-SYRK on their own (op 1 / 2, see get_plan) on blocks of A.
+static int run_subkernel(mpchol_ctx c, int op, int64_t a, int64_t k, double* A, int64_t lda,
+                         const mpchol_tree* tree, void* stream, mpchol_info* info) {
+  if (!c) return -1;
+  if (a < 0) return -2;
+  if (k < 0) return -3;
+  if (!A && a > 0 && k > 0) return -4;
+  if (lda < std::max<int64_t>(1, a + k)) return -5;
+  int v = validate_tree(tree);
+  if (v) return v == -7 ? -6 : v;
+  if (tree->n_nodes != 0) return -6;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (a == 0 || k == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->device));
+  Plan* P = nullptr;
+  int r = get_plan(c, a, lda, tree, &P, op, k);
+  if (r) return r;
+  r = ensure_ws(c, std::max<size_t>(P->ws_bytes, 256), std::max<int64_t>(P->parts, 1));
+  if (r) return r;
+  if (P->ninv > c->ninv) {
+    HIPCHK(hipDeviceSynchronize());
+    if (c->inv) HIPCHK(hipFree(c->inv));
+    c->inv = nullptr;
+    c->ninv = 0;
+    HIPCHK(hipMalloc((void**)&c->inv, sizeof(double) * kInvLd * kInvLd * (size_t)P->ninv));
+    c->ninv = P->ninv;
+  }
+  if (info) HIPCHK(hipEventRecord(c->ev0, s));
+  HIPCHK(launch_status_init(c->dst, s));
+  r = run_plan(c, *P, A, lda, s);
+  if (r) return r;
+  HIPCHK(hipMemcpyAsync(c->hst, c->dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  if (!info) return 0;
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  info->ms_factor = ms;
+  return status_from(*c->hst, info);
+}
+
+int mpchol_trsm(mpchol_ctx c, int64_t m, int64_t k, double* A, int64_t lda,
+                const mpchol_tree* tree, void* stream, mpchol_info* info) {
+  return run_subkernel(c, 1, m, k, A, lda, tree, stream, info);
+}
+
+int mpchol_syrk(mpchol_ctx c, int64_t n, int64_t k, double* A, int64_t lda,
+                const mpchol_tree* tree, void* stream, mpchol_info* info) {
+  return run_subkernel(c, 2, n, k, A, lda, tree, stream, info);
 }
 
 // Published-block copy and diagonal-block inverses of the block solves of order n.

@@ -525,6 +525,93 @@ struct Builder {
     }
   }
 
+  // ---- Tree-TRSM / Tree-SYRK on their own: the precision list is read by
+  // the depth of their own recursion (the GEMM at depth d, and a leaf SYRK
+  // reached at depth d, in offdiag[min(d, nlevels - 1)])
+  int level_prec(int depth) const { return t.offdiag[std::min(depth, t.nlevels - 1)]; }
+
+  // Inverse of the FP64 diagonal block (i0, m), m <= kInvLd, for the leaf
+  // TRSMs that follow (a kernel leaf, or two joined).
+  void leaf_inverse(int64_t i0, int64_t m) {
+    if (!use_inverse() || m > kInvLd || inv_slot.count({i0, m})) return;
+    auto trinv = [&](int64_t a0, int64_t mm, int slot, int64_t off) {
+      Launch L{Launch::TRINV, F64};
+      L.a0 = a0;
+      L.a1 = mm;
+      L.first = slot;
+      L.off = off;
+      P.launches.push_back(L);
+      P.stats.leaf_flops += (double)mm * mm * mm / 3.0;
+    };
+    const int js = P.ninv++;
+    if (m <= kKernelLeaf) {
+      trinv(i0, m, js, 0);
+    } else {
+      const int64_t m1 = leaf_split(m), m2 = m - m1;
+      trinv(i0, m1, js, 0);
+      trinv(i0 + m1, m2, js, m1 + m1 * (int64_t)kInvLd);
+      Launch J{Launch::INVJOIN, F64};
+      J.a0 = i0;
+      J.a1 = m;
+      J.a2 = m1;
+      J.first = js;
+      P.launches.push_back(J);
+    }
+    inv_slot[{i0, m}] = {js, 0};
+  }
+
+  void trsm_leaf_blocks(int64_t m, int64_t c0, int64_t k) {
+    if (m <= 0 || k <= 0) return;
+    if (std::min(m, k) <= t.leaf) {
+      leaf_inverse(c0, k);
+      return;
+    }
+    const int64_t k1 = split_rule(k, t.split_align);
+    trsm_leaf_blocks(m, c0, k1);
+    trsm_leaf_blocks(m, c0 + k1, k - k1);
+  }
+
+  void trsm_depth(int64_t r0, int64_t m, int64_t c0, int64_t k, int depth) {
+    if (m <= 0 || k <= 0) return;
+    if (std::min(m, k) <= t.leaf) {
+      leaf_trsm(r0, m, c0, k);
+      return;
+    }
+    const int prec = level_prec(depth);
+    const int64_t k1 = split_rule(k, t.split_align), k2 = k - k1;
+    trsm_depth(r0, m, c0, k1, depth + 1);
+    gemm_one(Node{r0, c0 + k1, (int)m, (int)k2, r0, c0, c0 + k1, c0, (int)k1, 0, prec},
+             prec != F64);
+    trsm_depth(r0, m, c0 + k1, k2, depth + 1);
+  }
+
+  void syrk_collect_depth(int64_t c0, int64_t s, int64_t p0, int64_t K, int depth,
+                          std::vector<Node>& out) {
+    if (s <= 0) return;
+    if (s <= t.leaf) {
+      const int p = t.syrk_leaf_mode ? t.leaf_prec : level_prec(depth);
+      out.push_back(Node{c0, c0, (int)s, (int)s, c0, p0, c0, p0, (int)K, 1, p});
+      return;
+    }
+    const int64_t s1 = split_rule(s, t.split_align), s2 = s - s1;
+    syrk_collect_depth(c0, s1, p0, K, depth + 1, out);
+    out.push_back(Node{c0 + s1, c0, (int)s2, (int)s1, c0 + s1, p0, c0, p0, (int)K, 0,
+                       level_prec(depth)});
+    syrk_collect_depth(c0 + s1, s2, p0, K, depth + 1, out);
+  }
+
+  void syrk_depth(int64_t c0, int64_t s, int64_t p0, int64_t K) {
+    if (s <= 0 || K <= 0) return;
+    std::vector<Node> all;
+    syrk_collect_depth(c0, s, p0, K, 0, all);
+    for (int q = E4M3; q <= F64; q++) {
+      std::vector<Node> sel;
+      for (auto& nd : all)
+        if (nd.prec == q) sel.push_back(nd);
+      emit_group(sel, q, q != F64);
+    }
+  }
+
   // ---- Algorithm 1
   void potrf(int64_t i0, int64_t m, int depth) {
     if (m <= 0) return;
@@ -560,6 +647,30 @@ static void tree_nodes_rec(int64_t i0, int64_t m, int32_t depth, const mpchol_tr
 void tree_nodes(int64_t n, const mpchol_tree* t, std::vector<PolicyNodeRec>& out) {
   out.clear();
   tree_nodes_rec(0, n, 0, t, out);
+}
+
+static void plan_init(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t) {
+  P.n = n;
+  P.ldl = ldl;
+  P.tree = *t;
+  P.node_prec.clear();
+  P.tree.node_prec = nullptr;
+  P.tree.n_nodes = 0;
+}
+
+void build_trsm_plan(Plan& P, int64_t m, int64_t k, int64_t ldl, const mpchol_tree* t) {
+  plan_init(P, m + k, ldl, t);
+  Builder B(P, P.tree, ldl);
+  B.trsm_leaf_blocks(m, 0, k);
+  B.trsm_depth(k, m, 0, k, 0);
+  P.stats.n_launch = (int64_t)P.launches.size();
+}
+
+void build_syrk_plan(Plan& P, int64_t n, int64_t k, int64_t ldl, const mpchol_tree* t) {
+  plan_init(P, n + k, ldl, t);
+  Builder B(P, P.tree, ldl);
+  B.syrk_depth(k, n, 0, k);
+  P.stats.n_launch = (int64_t)P.launches.size();
 }
 
 void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg, int tile) {

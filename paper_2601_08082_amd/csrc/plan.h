@@ -63,6 +63,14 @@ std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t);
 void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg = false,
                 int tile = 0);
 int64_t split_rule(int64_t m, int32_t align);
+// Tree-TRSM (Algorithm 2) / Tree-SYRK (Algorithm 3) on their own, on blocks of
+// one matrix (ld ldl) as Algorithm 1 calls them: TRSM A21 = (k, 0, m x k)
+// against L11 = (0, 0, k x k); SYRK A22 = (k, k, n x n) -= A21 A21^T with
+// A21 = (k, 0, n x k).  The precision list is read by their own recursion
+// depth; FP64 leaf TRSMs go through inverses of L11's leaf blocks formed first.
+void build_trsm_plan(Plan& P, int64_t m, int64_t k, int64_t ldl, const mpchol_tree* t);
+void build_syrk_plan(Plan& P, int64_t n, int64_t k, int64_t ldl, const mpchol_tree* t);
+
 
 // Internal Tree-POTRF nodes (order > leaf) of an order-n factorization in
 // preorder: {i0, m, m1, depth} each.

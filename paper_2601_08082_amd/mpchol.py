@@ -85,6 +85,8 @@ def _load() -> ct.CDLL:
                                   ct.POINTER(CInfo)]
     lib.mpchol_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, dbl, i32, vp,
                                  ct.POINTER(CInfo)]
+    lib.mpchol_trsm.argtypes = [vp, i64, i64, vp, i64, ct.POINTER(CTree), vp, ct.POINTER(CInfo)]
+    lib.mpchol_syrk.argtypes = [vp, i64, i64, vp, i64, ct.POINTER(CTree), vp, ct.POINTER(CInfo)]
     lib.mpchol_solve_noalloc.argtypes = [ct.c_int, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                          dbl, i32, vp, ct.POINTER(CInfo)]
     lib.mpchol_factor_batched.argtypes = [vp, i64, ct.POINTER(i64), ct.POINTER(vp),
@@ -262,6 +264,30 @@ class Context:
         if r == HIP_ERROR:
             raise RuntimeError("mpchol_solve: HIP error")
         return X_cm, info.as_dict()
+
+    def _sub(self, fn, name, A_cm, a: int, k: int, tree: Tree, stream, sync: bool):
+        _check_cm(A_cm, "A")
+        t, keep = tree.to_c()
+        info = CInfo()
+        r = fn(self._h, a, k, _ptr(A_cm), A_cm.shape[1], ct.byref(t), _stream_handle(stream),
+               ct.byref(info) if sync else None)
+        if r < 0:
+            raise ValueError(f"{name}: invalid argument {-r}")
+        if r == HIP_ERROR:
+            raise RuntimeError(f"{name}: HIP error")
+        if r == NOT_SUPPORTED:
+            raise NotImplementedError(f"{name}: descriptor feature not supported")
+        return info.as_dict() if sync else None
+
+    def trsm(self, A_cm, m: int, k: int, tree: Tree, stream=None, sync: bool = True):
+        """Tree-TRSM in place on blocks of A: A[k:k+m, :k] <- A[k:k+m, :k] L^-T with
+        L the lower triangle of A[:k, :k] (indices in the column-major matrix)."""
+        return self._sub(lib.mpchol_trsm, "mpchol_trsm", A_cm, m, k, tree, stream, sync)
+
+    def syrk(self, A_cm, n: int, k: int, tree: Tree, stream=None, sync: bool = True):
+        """Tree-SYRK in place on blocks of A: lower A[k:k+n, k:k+n] -=
+        A[k:k+n, :k] A[k:k+n, :k]^T."""
+        return self._sub(lib.mpchol_syrk, "mpchol_syrk", A_cm, n, k, tree, stream, sync)
 
     def quantize(self, X_cm, rows: int, cols: int, prec: int, scale_mode: int = 0,
                  stream=None):
