@@ -99,8 +99,10 @@ double orc_scale(double maxabs, int32_t prec, int32_t scale_mode) {
   while (maxabs > ldexp(R, e)) e++;
   while (maxabs <= ldexp(R, e - 1)) e--;
   /* FP32 operands are never scaled up: an operand at the top of FP32's range
-   * would overflow the FP32 accumulator.  Up-scaling is for the narrow formats. */
-  if ((scale_mode == 0 || prec == ORC_F32) && e < 0) e = 0;
+   * would overflow the FP32 accumulator.  Up-scaling is for the narrow formats:
+   * both of them in scale_mode 1, only E4M3 in scale_mode 2. */
+  if ((scale_mode == 0 || prec == ORC_F32 || (scale_mode == 2 && prec != ORC_E4M3)) && e < 0)
+    e = 0;
   return ldexp(1.0, e);
 }
 

@@ -28,7 +28,8 @@ typedef struct {
   int32_t offdiag[24];    /* precision of the updates issued at Tree-POTRF depth */
   int32_t leaf_prec;      /* ORC_F32 or ORC_F64: leaf POTRF and leaf TRSM        */
   int32_t syrk_leaf_mode; /* 0: leaf SYRK in the issuing level's precision       */
-  int32_t scale_mode;     /* 0: scale only down (paper), 1: power of two both ways */
+  int32_t scale_mode;     /* 0: scale only down (paper), 1: power of two both ways,
+                             2: both ways for E4M3 only (FP16 as in 0)            */
   const int8_t* node_prec;/* optional per-node precision, preorder node id; <0 = tree */
   int64_t n_nodes;        /* length of node_prec                                  */
 } orc_tree;

@@ -128,3 +128,18 @@ def test_scale_paper_alpha_is_one_in_range():
     for prec in (O.F16, O.E4M3):
         assert O.scale(O.rmax(prec), prec, 0) == 1.0
         assert O.scale(0.37, prec, 0) == 1.0
+
+
+@pytest.mark.parametrize("prec", [O.E4M3, O.F16, O.F32])
+def test_scale_mode_2_scales_only_e4m3_up(prec):
+    """scale_mode 2 is scale_mode 1 for E4M3 operands and scale_mode 0 for the
+    others: the block scale is 2^e with e the smallest power such that
+    max-abs <= Rmax 2^e, floored at 0 unless the operand is E4M3."""
+    R = O.rmax(prec)
+    for e in range(-12, 6):
+        for frac in (0.3, 0.5, 0.75, 1.0):
+            m = R * frac * 2.0 ** e
+            want_up = e if frac > 0.5 else e - 1       # smallest e' with m <= R 2^e'
+            want = 2.0 ** (want_up if prec == O.E4M3 else max(want_up, 0))
+            assert O.scale(m, prec, 2) == want, (prec, e, frac)
+            assert O.scale(m, prec, 2) == O.scale(m, prec, 1 if prec == O.E4M3 else 0)
