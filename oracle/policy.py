@@ -22,7 +22,13 @@ FP64 reference of every step of it:
                e(p) = 2 ||X||_F ||X - s Q_p(X / s)||_F / ||A_node||_F,
              s the power-of-two block scale of Section 3.4 (scale_mode given),
              ||A_node||_F over the symmetric node block;
-  budgets    tau * m1^2 / sum over nodes of m1^2;
+  budgets    tau * g * m1^2 / sum over nodes of m1^2, with g the pivot ratio
+             min_i l_ii^2 / max_i l_ii^2 of the FP64 factor.  Every pivot
+             l_ii^2 is the reciprocal of a diagonal entry of the inverse of a
+             leading block of A, so it lies between A's extreme eigenvalues
+             and g >= 1 / kappa_2(A).  Refinement (Section 2.2) contracts by
+             about kappa times the factor's relative error, so the budget
+             shrinks with the conditioning that g indicates;
   labels     the cheapest p (E4M3 < F16 < F32 < F64) with e(p) <= budget;
   mlp        x_hat = (x - mu) / sigma, h1 = relu(W1 x_hat + b1),
              h2 = relu(W2 h1 + b2), z = W3 h2 + b3, p = softmax(z); mean
@@ -131,9 +137,17 @@ def node_errors(A: np.ndarray, L: np.ndarray, n: int, leaf: int, align: int = 1,
     return np.array(out, dtype=np.float64).reshape(-1, 3)
 
 
-def budgets(n: int, leaf: int, align: int, tau: float) -> np.ndarray:
+def pivot_ratio(L: np.ndarray, n: int) -> float:
+    """min_i l_ii^2 / max_i l_ii^2 over the diagonal of the factor L[:n, :n]."""
+    if n == 0:
+        return 1.0
+    d = np.diag(np.asarray(L[:n, :n], dtype=np.float64)) ** 2
+    return float(d.min() / d.max())
+
+
+def budgets(n: int, leaf: int, align: int, tau: float, g: float = 1.0) -> np.ndarray:
     s2 = np.array([float(m1) ** 2 for (_, _, m1, _) in nodes(n, leaf, align)])
-    return tau * s2 / s2.sum() if s2.size else s2
+    return tau * g * s2 / s2.sum() if s2.size else s2
 
 
 def labels_from(err: np.ndarray, bud: np.ndarray) -> np.ndarray:

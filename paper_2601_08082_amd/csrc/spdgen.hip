@@ -1,10 +1,14 @@
 // GPU implementation of the seeded synthetic-input generator (SplitMix64,
-// Steele, Lea and Flood 2014), bitwise identical to spdgen.py.  Input
+// Steele, Lea and Flood 2014), bitwise identical to spdgen.py for the
+// diagonal-dominance family.  Input
 // generation only: none of the factorization's arithmetic lives here.
 //
 //   a_ij (i > j) = (u - 2^23) 2^-23, u = mix(seed ^ mix((i << 32) | j)) >> 40;
 //   a_ji = a_ij;  a_ii = RN(RN(ratio * S_i) + shift), S_i = sum_{j != i} |a_ij|
 //   (exact in FP64 in any order).  RHS(r, c) = same hash on (seed, (c << 32) | r).
+// Kernel family: points p_i = (hash(seed, (i << 32) | 0xFFFFFFF0),
+//   hash(seed, (i << 32) | 0xFFFFFFF1)); a_ij = exp(-|p_i - p_j|^2 / (2 ell^2)),
+//   a_ii = 1 + nugget (the device exp, within an ulp or two of the host's).
 // Built with -ffp-contract=off.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -50,6 +54,26 @@ __global__ __launch_bounds__(256) void k_gen(int64_t n, int64_t lda, double rati
   }
 }
 
+// One workgroup per column j of the squared-exponential kernel matrix.
+__global__ __launch_bounds__(256) void k_gen_kernel(int64_t n, int64_t lda, double ell,
+                                                    double nugget, uint64_t seed, double* A) {
+  const int64_t j = blockIdx.x;
+  const double xj = hval(seed, (uint64_t)j, 0xFFFFFFF0ull);
+  const double yj = hval(seed, (uint64_t)j, 0xFFFFFFF1ull);
+  const double c = 1.0 / (2.0 * ell * ell);
+  for (int64_t i = threadIdx.x; i < lda; i += 256) {
+    double v = 0.0;
+    if (i == j) {
+      v = 1.0 + nugget;
+    } else if (i < n) {
+      double dx = hval(seed, (uint64_t)i, 0xFFFFFFF0ull) - xj;
+      double dy = hval(seed, (uint64_t)i, 0xFFFFFFF1ull) - yj;
+      v = exp(-(dx * dx + dy * dy) * c);
+    }
+    A[i + j * lda] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rhs(int64_t n, int64_t nrhs, int64_t ldb, uint64_t seed,
                                              double* B) {
   const int64_t c = blockIdx.y;
@@ -69,6 +93,17 @@ int spdgen_fill(int64_t n, int64_t lda, double ratio, double shift, uint64_t see
   if (n == 0) return 0;
   hipLaunchKernelGGL(k_gen, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream, n, lda, ratio,
                      shift, seed, A);
+  return (int)hipGetLastError();
+}
+
+// Fill A (lda x n, column-major, device) with the squared-exponential kernel
+// matrix plus nugget.  Returns 0, -1 for bad sizes or ell <= 0, or the HIP error.
+int spdgen_kernel_fill(int64_t n, int64_t lda, double ell, double nugget, uint64_t seed,
+                       double* A, void* stream) {
+  if (n < 0 || lda < (n > 0 ? n : 1) || !(ell > 0.0)) return -1;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_gen_kernel, dim3((unsigned)n), dim3(256), 0, (hipStream_t)stream, n, lda,
+                     ell, nugget, seed, A);
   return (int)hipGetLastError();
 }
 

@@ -5,7 +5,8 @@ This module is the one piece shared by the CPU oracle and the GPU path.  It hold
 none of the factorization's arithmetic: it only turns (seed, index) pairs into
 matrix entries, from a published counter-based generator (SplitMix64, Steele,
 Lea and Flood, OOPSLA 2014).  The GPU generator kernel in ``csrc/spdgen.hip``
-implements the same definition and produces bitwise-identical matrices.
+implements the same definition and produces bitwise-identical matrices (the
+dominance family below; the kernel family agrees to an ulp or two).
 
 Definition (0-based indices, column-major storage):
 
@@ -16,6 +17,16 @@ Definition (0-based indices, column-major storage):
   is a multiple of 2^-23 and S_i < 2^17),  a_ii = RN(RN(ratio * S_i) + shift).
   ratio > 1 makes the matrix strictly diagonally dominant, hence SPD.
 * right-hand side column c, row r:  the same hash on (seed_rhs, key (c << 32) | r).
+
+A second family, ``gen_kernel``, is not diagonally dominant: the covariance
+matrix of a Gaussian process with a squared-exponential kernel at n points of
+the square [-1, 1)^2, plus a nugget (the matrices Gaussian-process regression
+factors).  Point i is (hash(seed, (i << 32) | K0), hash(seed, (i << 32) | K1))
+with K0 = 0xFFFFFFF0, K1 = 0xFFFFFFF1;  a_ij = exp(-|p_i - p_j|^2 / (2 ell^2))
+for i != j,  a_ii = 1 + nugget.  Its eigenvalues decay fast, so the smallest
+is about the nugget and the conditioning is about lambda_max / nugget.  The
+GPU fill evaluates the same formula with the device's exp (equal to numpy's
+up to an ulp or two, not bitwise).
 
 The paper evaluates on dense SPD matrices with uniform random entries and a
 large diagonal (Section 4.1); the dominance-ratio form keeps that structure and
@@ -82,6 +93,35 @@ def gen_rhs(n: int, nrhs: int, seed: int = 101, ldb: int | None = None) -> np.nd
     for c in range(nrhs):
         B[:n, c] = hash_unit(seed, np.full(r.shape, c, dtype=np.int64), r)
     return B
+
+
+KEY_X = 0xFFFFFFF0
+KEY_Y = 0xFFFFFFF1
+
+
+def kernel_points(n: int, seed: int) -> np.ndarray:
+    """(n, 2) points of ``gen_kernel``, uniform on [-1, 1)^2."""
+    i = np.arange(n, dtype=np.int64)
+    return np.stack([hash_unit(seed, i, np.full(n, KEY_X, dtype=np.int64)),
+                     hash_unit(seed, i, np.full(n, KEY_Y, dtype=np.int64))], axis=1)
+
+
+def gen_kernel(n: int, ell: float, nugget: float, seed: int = 1,
+               lda: int | None = None) -> np.ndarray:
+    """Squared-exponential covariance matrix plus nugget, column-major (lda, n)."""
+    lda = n if lda is None else lda
+    if lda < n:
+        raise ValueError("lda < n")
+    A = np.zeros((lda, n), dtype=np.float64, order="F")
+    if n == 0:
+        return A
+    P = kernel_points(n, seed)
+    dx = P[:, 0][:, None] - P[:, 0][None, :]
+    dy = P[:, 1][:, None] - P[:, 1][None, :]
+    K = np.exp(-(dx * dx + dy * dy) / (2.0 * ell * ell))
+    K[np.arange(n), np.arange(n)] = 1.0 + nugget
+    A[:n, :n] = K
+    return A
 
 
 def gershgorin_lower_bound(n: int, ratio: float, shift: float, A: np.ndarray) -> float:

@@ -21,6 +21,8 @@ def _load():
     lib = ct.CDLL(LIB_PATH)
     lib.spdgen_fill.argtypes = [ct.c_int64, ct.c_int64, ct.c_double, ct.c_double, ct.c_uint64,
                                 ct.c_void_p, ct.c_void_p]
+    lib.spdgen_kernel_fill.argtypes = [ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
+                                       ct.c_uint64, ct.c_void_p, ct.c_void_p]
     lib.spdgen_rhs.argtypes = [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_uint64, ct.c_void_p,
                                ct.c_void_p]
     return lib
@@ -46,6 +48,19 @@ def gen_spd(n: int, ratio: float, shift: float = 0.0, seed: int = 1, lda: int | 
                            torch.cuda.current_stream().cuda_stream)
     if r != 0:
         raise RuntimeError(f"spdgen_fill failed ({r})")
+    return A
+
+
+def gen_kernel(n: int, ell: float, nugget: float, seed: int = 1, lda: int | None = None,
+               device="cuda"):
+    """Device tensor (n, lda): the squared-exponential kernel matrix plus nugget."""
+    import torch
+    lda = n if lda is None else lda
+    A = torch.empty((max(n, 1), lda), dtype=torch.float64, device=device)
+    r = _get().spdgen_kernel_fill(n, lda, ell, nugget, seed, A.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+    if r != 0:
+        raise RuntimeError(f"spdgen_kernel_fill failed ({r})")
     return A
 
 

@@ -119,6 +119,53 @@ def test_budgets_and_labels():
     np.testing.assert_array_equal(P.labels_from(err, bud), [O.E4M3, O.F16, O.F64, O.F32])
 
 
+def test_pivot_ratio_closed_form_and_definition():
+    # diagonal A: the pivots are the diagonal itself
+    d = np.array([4.0, 0.25, 9.0, 1.0])
+    L = np.diag(np.sqrt(d))
+    assert P.pivot_ratio(L, 4) == pytest.approx(0.25 / 9.0, rel=1e-15)
+    assert P.pivot_ratio(np.zeros((1, 1)), 0) == 1.0
+    # pivot i = 1 / (inverse of the leading (i+1) block)[i, i], an independent route
+    from paper_2601_08082_amd import spdgen
+    n = 40
+    A = spdgen.gen_kernel(n, 0.4, 0.05, seed=3)
+    L = O.factor(A, tree=O.Tree(leaf=8, offdiag=[O.F64]))[0]
+    piv = np.array([1.0 / np.linalg.inv(A[:i + 1, :i + 1])[i, i] for i in range(n)])
+    assert P.pivot_ratio(L, n) == pytest.approx(piv.min() / piv.max(), rel=1e-9)
+
+
+@pytest.mark.parametrize("kind", ["dominance", "kernel"])
+def test_pivot_ratio_brackets_inverse_condition(kind):
+    # every pivot lies in [lambda_min, lambda_max], so 1/kappa_2 <= g <= 1
+    from paper_2601_08082_amd import spdgen
+    n = 120
+    A = (spdgen.gen_spd(n, 1.02, 0.0, seed=4) if kind == "dominance"
+         else spdgen.gen_kernel(n, 0.3, 1e-3, seed=4))
+    w = np.linalg.eigvalsh(A[:n, :n])
+    L = O.factor(A, tree=O.Tree(leaf=16, offdiag=[O.F64]))[0]
+    g = P.pivot_ratio(L, n)
+    assert w[0] / w[-1] <= g * (1 + 1e-9) and g <= 1.0
+    b = P.budgets(n, 16, 1, 1e-2, g)
+    assert b.sum() == pytest.approx(1e-2 * g, rel=1e-14)
+
+
+def test_kernel_family_labels_need_more_precision():
+    # an ill-conditioned covariance matrix: with the pivot-ratio budget the
+    # root and most nodes need at least F32, where a dominant matrix of the
+    # same size takes E4M3 or F16 everywhere
+    from paper_2601_08082_amd import spdgen
+    n, leaf = 256, 32
+    Ak = spdgen.gen_kernel(n, 0.3, 1e-3, seed=6)
+    Lk = O.factor(Ak, tree=O.Tree(leaf=leaf, offdiag=[O.F64]))[0]
+    lk = P.labels_from(P.node_errors(Ak, Lk, n, leaf, scale_mode=2),
+                       P.budgets(n, leaf, 1, 1e-2, P.pivot_ratio(Lk, n)))
+    Ad = spdgen.gen_spd(n, 1.5, 0.0, seed=6)
+    Ld = O.factor(Ad, tree=O.Tree(leaf=leaf, offdiag=[O.F64]))[0]
+    ld = P.labels_from(P.node_errors(Ad, Ld, n, leaf, scale_mode=2),
+                       P.budgets(n, leaf, 1, 1e-2, P.pivot_ratio(Ld, n)))
+    assert lk[0] >= O.F32 and np.sum(lk >= O.F32) > len(lk) / 2 and np.all(ld <= O.F16)
+
+
 def test_labels_monotone_in_dominance():
     # a more dominant diagonal shrinks L21 relative to A: labels never get more precise
     from paper_2601_08082_amd import spdgen
