@@ -71,7 +71,9 @@ enum {
  *   scale_mode   0: block scale s = 2^e, the smallest power of two with
  *                max|B| <= Rmax*s, and s >= 1 (Section 3.4 with alpha rounded
  *                up to a power of two); 1: also scale up (e < 0) for FP16 and
- *                E4M3 operands.  FP32 operands are never scaled up.
+ *                E4M3 operands; 2: scale up E4M3 operands only (FP16 as in 0,
+ *                so its casts stay single-pass).  FP32 operands are never
+ *                scaled up.
  *   scale_tile   must be 0 (one scale per GEMM operand block).
  *   leaf_trsm    0: an FP64 leaf TRSM (Algorithm 2 base case) multiplies by
  *                the leaf's inverse, formed once per kernel leaf (FP64 MFMA,
@@ -357,7 +359,9 @@ int mpchol_policy_features(mpchol_ctx ctx, int64_t n, const double* A, int64_t l
  * p in {E4M3, F16, F32}: e(p) = 2 ||X||_F ||X - s Q_p(X/s)||_F / ||A_node||_F
  * (s: the block's power-of-two scale under scale_mode, Section 3.4; A_node
  * the node's symmetric diagonal block); label = the cheapest p with
- * e(p) <= tau * m1_k^2 / sum_j m1_j^2, else F64.
+ * e(p) <= tau * g * m1_k^2 / sum_j m1_j^2, else F64, where g = min_i l_ii^2 /
+ * max_i l_ii^2 is L's pivot ratio (g >= 1 / kappa_2(A): the budget shrinks
+ * with the conditioning, as refinement's contraction does, Section 2.2).
  * err: NULL or nodes x 3 doubles; labels: nodes int32.  Asynchronous.
  * Errors: -2 n; -3 A; -4 lda; -5 L; -6 ldl; -7 tree; -8 tau <= 0;
  * -9 scale_mode; -10 labels. */

@@ -43,6 +43,8 @@ struct mpchol_ctx_s {
   int64_t part_count = 0;
   double* rbuf = nullptr;     // refinement residual / correction (n x nrhs)
   int64_t rbuf_count = 0;
+  double* rpart = nullptr;    // residual partial sums (residual_part_bytes(n))
+  size_t rpart_bytes = 0;
   // block solves: published solution blocks and diagonal-block inverses
   double* tsv_x = nullptr;    // published solution blocks (n x kMaxRhs)
   size_t tsv_x_count = 0;
@@ -310,7 +312,6 @@ static int status_from(const DevStatus& h, mpchol_info* info) {
   return st;
 }
 
-// the tune-table entry for a system of order n (NULL: the descriptor applies)
 // Device buffer `slot` of the policy path with at least `bytes` (grown after
 // the device has drained, so no queued kernel still uses the old one).
 static void* pol_buf(mpchol_ctx c, size_t slot, size_t bytes) {
@@ -474,7 +475,7 @@ int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, 
   if (ldl < std::max<int64_t>(1, n)) return -6;
   if (validate_tree(tree)) return -7;
   if (!(tau > 0.0)) return -8;
-  if (scale_mode != 0 && scale_mode != 1) return -9;
+  if (scale_mode < 0 || scale_mode > 2) return -9;
   PolicyTables T;
   policy_tables(n, tree, T);
   const int nn = (int)T.nodes.size();
@@ -495,7 +496,8 @@ int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, 
   double* dx = (double*)pol_buf(c, 6, sizeof(double) * 4 * (size_t)xparts);
   double* da = (double*)pol_buf(c, 7, sizeof(double) * 4 * (size_t)aparts);
   double* sc = (double*)pol_buf(c, 8, sizeof(double) * 3 * (size_t)nn);
-  if (!dx || !da || !sc) return MPCHOL_HIP_ERROR;
+  double* gd = (double*)pol_buf(c, 18, sizeof(double));
+  if (!dx || !da || !sc || !gd) return MPCHOL_HIP_ERROR;
   PNode* dn = nullptr;
   StatJob *dxj = nullptr, *dxj2 = nullptr, *daj = nullptr;
   if (upload_async(c, 4, T.nodes, &dn, s) || upload_async(c, 9, xj, &dxj, s) ||
@@ -505,7 +507,8 @@ int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, 
   HIPCHK(launch_node_scales(nn, dxj, dx, scale_mode, sc, s));
   HIPCHK(launch_stats(L, ldl, dxj2, nn, xparts2, sc, dx, s));
   HIPCHK(launch_stats(A, lda, daj, nn, aparts, nullptr, da, s));
-  HIPCHK(launch_node_labels(dn, nn, dxj2, dx, daj, da, tau, sum_s2, err, labels, s));
+  HIPCHK(launch_pivot_ratio(L, ldl, n, gd, s));
+  HIPCHK(launch_node_labels(dn, nn, dxj2, dx, daj, da, tau, gd, sum_s2, err, labels, s));
   return 0;
 }
 
@@ -601,6 +604,7 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->inv) (void)hipFree(c->inv);
   if (c->part) (void)hipFree(c->part);
   if (c->rbuf) (void)hipFree(c->rbuf);
+  if (c->rpart) (void)hipFree(c->rpart);
   if (c->tsv_x) (void)hipFree(c->tsv_x);
   if (c->tsv_yd) (void)hipFree(c->tsv_yd);
   if (c->npart) (void)hipFree(c->npart);
@@ -760,6 +764,8 @@ struct SolveBufs {
   double* md;          //   matrices (2 nblk 4096)
   double* xp;          // published solution blocks (n kMaxRhs)
   double* rbuf;        // residual / correction (n nrhs)
+  double* rpart;       // residual partial sums (NULL: the two-read residual)
+  size_t rpart_bytes;
   double* npart;       // norm partials (kNormParts kMaxRhs 2), device
   double* hnpart;      //   and host
   mpchol_ctx prof;     // launch timing (NULL: none)
@@ -838,7 +844,7 @@ static int solve_run(const SolveBufs& Bf, int64_t n, int64_t nrhs, const double*
         int nc = (int)std::min<int64_t>(kMaxRhs, nrhs - c0);
         int pk = sb_prof_begin(Bf, MPCHOL_PROF_RESIDUAL, (double)n * (n + 1) / 2 * 8.0, s);
         HIPCHK(launch_residual(A, lda, n, nc, X + c0 * ldx, ldx, B + c0 * ldb, ldb, R + c0 * n, n,
-                               s));
+                               Bf.rpart, Bf.rpart_bytes, s));
         sb_prof_end(Bf, pk, s);
       }
       r = chol_solve_inplace(Bf, n, nrhs, L, ldl, R, n, s);
@@ -912,9 +918,17 @@ int mpchol_solve(mpchol_ctx c, int64_t n, int64_t nrhs, const double* A, int64_t
     HIPCHK(hipMalloc((void**)&c->rbuf, sizeof(double) * n * nrhs));
     c->rbuf_count = n * nrhs;
   }
+  if (A && max_iter > 0 && c->rpart_bytes < residual_part_bytes(n)) {
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->rpart) HIPCHK(hipFree(c->rpart));
+    c->rpart = nullptr;
+    c->rpart_bytes = 0;
+    HIPCHK(hipMalloc((void**)&c->rpart, residual_part_bytes(n)));
+    c->rpart_bytes = residual_part_bytes(n);
+  }
   const SolveBufs Bf{c->device, c->dst, c->hst, c->tsv_yd,
-                     c->tsv_yd + (size_t)((n + 63) / 64) * 4096, c->tsv_x, c->rbuf, c->npart,
-                     c->hnpart, c};
+                     c->tsv_yd + (size_t)((n + 63) / 64) * 4096, c->tsv_x, c->rbuf, c->rpart,
+                     c->rpart_bytes, c->npart, c->hnpart, c};
   const int status = solve_run(Bf, n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, tol, max_iter, s, info);
   if (status == MPCHOL_HIP_ERROR || status < 0) return status;
   HIPCHK(hipEventRecord(c->ev1, s));
@@ -946,7 +960,7 @@ int mpchol_solve_noalloc(int device, int64_t n, int64_t nrhs, const double* A, i
   DevStatus hst;
   double hnpart[kNormParts * kMaxRhs * 2];
   const SolveBufs Bf{device, sc.status, &hst, sc.yd, sc.yd + (size_t)((n + 63) / 64) * 4096, sc.xp,
-                     sc.rbuf, sc.npart, hnpart, nullptr};
+                     sc.rbuf, nullptr, 0, sc.npart, hnpart, nullptr};
   const int status = solve_run(Bf, n, nrhs, A, lda, L, ldl, B, ldb, X, ldx, tol, max_iter, s, info);
   if (info)
     info->ms_solve = (float)std::chrono::duration<double, std::milli>(
@@ -1197,7 +1211,7 @@ int mpchol_quantize(mpchol_ctx c, int64_t rows, int64_t cols, const double* src,
   if (!src && rows > 0 && cols > 0) return -4;
   if (lds < std::max<int64_t>(1, rows)) return -5;
   if (prec != MPCHOL_F16 && prec != MPCHOL_E4M3) return -6;
-  if (scale_mode < 0 || scale_mode > 1) return -7;
+  if (scale_mode < 0 || scale_mode > 2) return -7;
   if (!dst && rows > 0) return -8;
   if (ldq < ((cols + 15) / 16) * 16) return -9;
   if (rows > INT32_MAX || cols > INT32_MAX || ldq > INT32_MAX) return -2;

@@ -142,9 +142,14 @@ struct NoAllocScratch {
   double* npart;   // 64 16 2
 };
 hipError_t noalloc_scratch(int device, NoAllocScratch* out);
+// R = B - A X (A symmetric, lower triangle).  With a partial-sum buffer of at
+// least residual_part_bytes(n) the lower triangle is read once (super-tile
+// kernel and a reduce); without one each tile is read twice (by its block row
+// and its block column).
+size_t residual_part_bytes(int64_t n);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
-                           hipStream_t s);
+                           double* part, size_t part_bytes, hipStream_t s);
 hipError_t launch_update_norms(int64_t n, int nrhs, double* X, int64_t ldx, const double* D,
                                int64_t ldd, double* part, int nparts, double* out,
                                hipStream_t s);

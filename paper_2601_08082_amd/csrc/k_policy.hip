@@ -193,11 +193,36 @@ __global__ void k_node_scales(int n_nodes, const StatJob* __restrict__ jobs,
   for (int p = 0; p < 3; p++) scales[k * 3 + p] = block_scale(mx, p, scale_mode);
 }
 
+// g <- min_i l_ii^2 / max_i l_ii^2 over the diagonal of the factor L (one
+// workgroup; the pivot ratio that scales the label budget).
+__global__ __launch_bounds__(256) void k_pivot_ratio(const double* __restrict__ L, int64_t ldl,
+                                                     int64_t n, double* __restrict__ g) {
+  __shared__ double smin[256], smax[256];
+  double mn = kInf, mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double l = L[i + i * ldl];
+    const double d = l * l;
+    mn = fmin(mn, d);
+    mx = fmax(mx, d);
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + k]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[0] = smin[0] / smax[0];
+}
+
 __global__ void k_node_labels(const PNode* __restrict__ nodes, int n_nodes,
                               const StatJob* __restrict__ xjobs, const double* __restrict__ xparts,
                               const StatJob* __restrict__ ajobs, const double* __restrict__ aparts,
-                              double tau, double sum_s2, double* __restrict__ err,
-                              int32_t* __restrict__ labels) {
+                              double tau, const double* __restrict__ g, double sum_s2,
+                              double* __restrict__ err, int32_t* __restrict__ labels) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_nodes) return;
   const StatJob X = xjobs[k], Aj = ajobs[k];
@@ -212,7 +237,7 @@ __global__ void k_node_labels(const PNode* __restrict__ nodes, int n_nodes,
   for (int p = 0; p < Aj.nparts; p++) as += aparts[(int64_t)(Aj.part0 + p) * 4];
   const double an = sqrt(as), xn = sqrt(xs);
   const double s = (double)nodes[k].m1;
-  const double budget = tau * (s * s) / sum_s2;
+  const double budget = tau * g[0] * (s * s) / sum_s2;
   int lab = 3;
   for (int p = 2; p >= 0; p--) {
     const double ep = an > 0.0 ? 2.0 * xn * sqrt(e[p]) / an : kInf;
@@ -478,11 +503,17 @@ hipError_t launch_node_scales(int n_nodes, const StatJob* jobs, const double* pa
 
 hipError_t launch_node_labels(const PNode* nodes, int n_nodes, const StatJob* xjobs,
                               const double* xparts, const StatJob* ajobs, const double* aparts,
-                              double tau, double sum_s2, double* err, int32_t* labels,
-                              hipStream_t s) {
+                              double tau, const double* g, double sum_s2, double* err,
+                              int32_t* labels, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_node_labels, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s,
-                     nodes, n_nodes, xjobs, xparts, ajobs, aparts, tau, sum_s2, err, labels);
+                     nodes, n_nodes, xjobs, xparts, ajobs, aparts, tau, g, sum_s2, err, labels);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot_ratio(const double* L, int64_t ldl, int64_t n, double* g, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pivot_ratio, dim3(1), dim3(256), 0, s, L, ldl, n, g);
   return hipGetLastError();
 }
 

@@ -756,6 +756,177 @@ __global__ __launch_bounds__(256) void k_resid3(const double* __restrict__ A, in
   }
 }
 
+// ------------------------------------------------------------------------
+// R = B - A X reading A's lower triangle once.  The 64 x 64 tiles of the lower
+// triangle are grouped into S x S super-tiles (S = 2, 4 or 8); workgroup w
+// takes super-tile (P, Q), P >= Q (row-major over the lower triangle), and
+// from every tile (I, q) of it forms
+//   forward     A(I, q) X(q)     into the rows of block I (super-row P), and
+//   transposed  A(I, q)^T X(I)   into the rows of block q (super-row Q), I > q
+// (a diagonal tile, I = q, holds the symmetric block: forward only, mirrored).
+// The transposed product wants the tile with its lanes on the columns: a
+// second read of the same tile, which the workgroup has just fetched, so it
+// comes from L2 and HBM sees each tile once.  The forward sums of the
+// super-row live in LDS (each lane owns its slots, so they need no barrier),
+// the transposed sum of the current tile column in registers.  Partial sums
+// go to part[(R nsup + j) S 64 + row][c] (16 columns per row): slot (P, Q)
+// holds the forward sums of (P, Q), slot (Q, P) the transposed ones (both in
+// slot (P, P) for a diagonal super-tile), so every (R, j) is written once and
+// k_resid_reduce sums row i's nsup slots in a fixed order: deterministic.
+constexpr int kRSMax = 8;
+
+// LDS-only workgroup barrier: waits for this wave's LDS accesses, not for its
+// global loads in flight.
+__device__ inline void lds_barrier() {
+  lds_settle();
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ __launch_bounds__(256, 1) void k_resid4(const double* __restrict__ A, int64_t lda,
+                                                   int64_t n, int nrhs,
+                                                   const double* __restrict__ X, int64_t ldx,
+                                                   int S, int nsup, double* __restrict__ part) {
+  __shared__ double xsI[kRSMax][NB * XSW];   // X blocks of the super-row
+  __shared__ double xsQ[2][NB * XSW];        // X block of the current tile column
+  __shared__ double yF[kRSMax][4 * 256];     // forward sums, lane-private slots
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+  const int nblk = (int)((n + NB - 1) / NB);
+  const int w = blockIdx.x;
+  int P = (int)((sqrt(8.0 * (double)w + 1.0) - 1.0) * 0.5);
+  while ((P + 1) * (P + 2) / 2 <= w) P++;
+  while (P * (P + 1) / 2 > w) P--;
+  const int Q = w - P * (P + 1) / 2;
+  const bool diag = P == Q;
+  const int I0 = P * S, q0 = Q * S;
+  const int nI = min(S, nblk - I0), nQ = min(S, nblk - q0);
+  const int SR = S * NB;
+  auto rows_of = [&](int b) { return (int)min((int64_t)NB, n - (int64_t)b * NB); };
+  auto x_load = [&](int b, double (&xv)[4]) {
+    const int64_t b0 = (int64_t)b * NB;
+    const int nk = rows_of(b);
+    int xi, xc[4];
+    bool xu[4];
+    xblock_coords(nk, nrhs, xc, xi, xu);
+#pragma unroll
+    for (int u = 0; u < 4; u++) xv[u] = X[(b0 + min(xi, nk - 1)) + (int64_t)min(xc[u], nrhs - 1) * ldx];
+  };
+  auto x_stage = [&](int b, const double (&xv)[4], double* dst) {
+    int xi, xc[4];
+    bool xu[4];
+    xblock_coords(rows_of(b), nrhs, xc, xi, xu);
+#pragma unroll
+    for (int u = 0; u < 4; u++) dst[xi * XSW + xc[u]] = keep_or_zero(xv[u], xu[u]);
+  };
+  for (int ii = 0; ii < nI; ii++) {
+    double xv[4];
+    x_load(I0 + ii, xv);
+    x_stage(I0 + ii, xv, xsI[ii]);
+#pragma unroll
+    for (int r = 0; r < 4; r++) yF[ii][r * 256 + tid] = 0.0;
+  }
+  double xq[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!diag) x_load(q0, xq);
+  lds_barrier();
+
+  // tile walk: column qq of the super-tile, rows ii (from qq on a diagonal one)
+  struct It { int qq, ii; };
+  auto adv = [&](It& it) {
+    if (++it.ii == nI) {
+      it.qq++;
+      it.ii = diag ? it.qq : 0;
+    }
+  };
+  // both reads of a tile: 32 loads for every tile (a diagonal tile's second
+  // read is not used), so the count of loads in flight is the same everywhere
+  auto issue = [&](const It& it, double (&f)[16], double (&t)[16]) {
+    const int I = I0 + it.ii, q = q0 + it.qq;
+    const double* T = A + (int64_t)I * NB + (int64_t)q * NB * lda;
+    const int ni = rows_of(I), nq = rows_of(q);
+    tile_load(T, 1u, (uint32_t)lda, false, I == q, ni, nq, f);
+    tile_load(T, (uint32_t)lda, 1u, true, false, nq, ni, t);
+  };
+  const int T = diag ? nI * (nI + 1) / 2 : nI * nQ;
+  It cur{0, 0}, ahead{0, 0};
+  f64x4_t accT = {0.0, 0.0, 0.0, 0.0};
+  const int orow = 16 * wv + (l >> 4), ocol = l & 15;
+  auto step = [&](int t, double (&f)[16], double (&tr)[16], double (&pf)[16], double (&ptr)[16]) {
+    if (t + 2 < T) {
+      issue(ahead, pf, ptr);
+      adv(ahead);
+    }
+    __builtin_amdgcn_sched_barrier(0);    // those loads stay ahead of the products
+    const int qq = cur.qq, ii = cur.ii;
+    const int I = I0 + ii, q = q0 + qq;
+    if (ii == (diag ? qq : 0)) {
+      // a new tile column: its X block (a diagonal super-tile has it already)
+      accT = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      if (!diag) {
+        x_stage(q, xq, xsQ[qq & 1]);
+        lds_barrier();
+        if (qq + 1 < nQ) x_load(q + 1, xq);
+      }
+    }
+    f64x4_t a = {0.0, 0.0, 0.0, 0.0};
+    tile_mfma(f, diag ? xsI[qq] : xsQ[qq & 1], false, rows_of(q), a);
+#pragma unroll
+    for (int r = 0; r < 4; r++) yF[ii][r * 256 + tid] += a[r];
+    if (I != q) tile_mfma(tr, xsI[ii], true, rows_of(I), accT);
+    if (ii == nI - 1) {
+      // the column is done: its transposed sum (block q is never ragged here)
+      if (diag) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) yF[qq][r * 256 + tid] += accT[r];
+      } else {
+        double* dst = part + (((int64_t)Q * nsup + P) * SR + (int64_t)qq * NB) * MAXRHS;
+#pragma unroll
+        for (int r = 0; r < 4; r++) dst[(orow + 4 * r) * MAXRHS + ocol] = accT[r];
+      }
+    }
+    adv(cur);
+  };
+  double fa[16], ta[16], fb[16], tb[16], fc[16], tc[16];
+  issue(ahead, fa, ta);
+  adv(ahead);
+  if (T > 1) {
+    issue(ahead, fb, tb);
+    adv(ahead);
+  }
+  int t = 0;
+  for (; t + 2 < T; t += 3) {
+    step(t, fa, ta, fc, tc);
+    step(t + 1, fb, tb, fa, ta);
+    step(t + 2, fc, tc, fb, tb);
+  }
+  if (t < T) step(t, fa, ta, fc, tc);
+  if (t + 1 < T) step(t + 1, fb, tb, fa, ta);
+  // forward sums of the super-row (rows past n land in slots nobody reads)
+  double* dst = part + ((int64_t)P * nsup + Q) * SR * MAXRHS;
+  for (int ii = 0; ii < nI; ii++)
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+      dst[((int64_t)ii * NB + orow + 4 * r) * MAXRHS + ocol] = yF[ii][r * 256 + tid];
+}
+
+// R(i, c) = B(i, c) - sum over j of part[(R nsup + j) S 64 + i - R S 64][c],
+// R = i / (S 64): 16 rows x 16 columns per workgroup.
+__global__ __launch_bounds__(256) void k_resid_reduce(int64_t n, int nrhs, int S, int nsup,
+                                                      const double* __restrict__ part,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ R, int64_t ldr) {
+  const int c = threadIdx.x & 15;
+  const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (i >= n || c >= nrhs) return;
+  const int64_t SR = (int64_t)S * NB;
+  const int64_t Rs = i / SR, rl = i - Rs * SR;
+  const double* p = part + ((Rs * nsup) * SR + rl) * MAXRHS + c;
+  const int64_t stride = SR * MAXRHS;
+  double sum = 0.0;
+#pragma unroll 8
+  for (int j = 0; j < nsup; j++) sum += p[j * stride];
+  R[i + c * ldr] = B[i + c * ldb] - sum;
+}
+
 // X += D; part[w * 2 * nrhs + 2 c + {0, 1}] = max |D|, max |X| over the
 // workgroup's rows (NaN/Inf map to +Inf).
 __global__ __launch_bounds__(256) void k_update_norms(int64_t n, int nrhs, double* X,
@@ -804,11 +975,43 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t n, int nrhs, const do
 }
 
 
+// Super-tile side for an order-n residual: the largest S in {8, 4, 2} that
+// still gives at least 512 workgroups (two per compute unit), else 2.
+static int resid_super(int64_t n, int* nsup) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  int S = 2;
+  for (int c : {8, 4}) {
+    const int64_t ns = (nblk + c - 1) / c;
+    if (ns * (ns + 1) / 2 >= 512) {
+      S = c;
+      break;
+    }
+  }
+  *nsup = (int)((nblk + S - 1) / S);
+  return S;
+}
+
+size_t residual_part_bytes(int64_t n) {
+  if (n <= 0) return 0;
+  int nsup = 0;
+  const int S = resid_super(n, &nsup);
+  return (size_t)nsup * nsup * S * NB * MAXRHS * sizeof(double);
+}
+
 hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
-                           hipStream_t s) {
+                           double* part, size_t part_bytes, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (nrhs > MAXRHS) return hipErrorInvalidValue;
+  if (part && part_bytes >= residual_part_bytes(n)) {
+    int nsup = 0;
+    const int S = resid_super(n, &nsup);
+    hipLaunchKernelGGL(k_resid4, dim3((unsigned)((int64_t)nsup * (nsup + 1) / 2)), dim3(256), 0, s,
+                       A, lda, n, nrhs, X, ldx, S, nsup, part);
+    hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, n, nrhs,
+                       S, nsup, (const double*)part, B, ldb, R, ldr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_resid3, dim3((unsigned)((n + NB - 1) / NB)), dim3(256), 0, s, A, lda, n, nrhs,
                      X, ldx, B, ldb, R, ldr);
   return hipGetLastError();

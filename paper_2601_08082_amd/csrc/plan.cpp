@@ -46,7 +46,7 @@ int validate_tree(const mpchol_tree* t) {
     if (t->offdiag[i] < MPCHOL_E4M3 || t->offdiag[i] > MPCHOL_F64) return -7;
   if (t->leaf_prec != MPCHOL_F32 && t->leaf_prec != MPCHOL_F64) return -7;
   if (t->syrk_leaf_mode < 0 || t->syrk_leaf_mode > 1) return -7;
-  if (t->scale_mode < 0 || t->scale_mode > 1) return -7;
+  if (t->scale_mode < 0 || t->scale_mode > 2) return -7;
   if (t->scale_tile != 0) return MPCHOL_NOT_SUPPORTED;
   if (t->leaf_trsm != 0 && t->leaf_trsm != 1) return -7;
   if (t->n_nodes < 0 || (t->n_nodes > 0 && !t->node_prec)) return -7;
@@ -163,10 +163,10 @@ struct Builder {
     // pass: FP32 blocks are never scaled up, so a block's scale is 1 unless
     // its max-abs exceeds the FP32 range
     const bool quant = prec == F16 || prec == E4M3 || (prec == F32 && !single_wg);
-    // FP16 with scale_mode 0 (and FP32): one pass casts at scale 1 and
-    // records the max-abs
+    // FP16 without upward scaling (scale_mode 0 or 2) and FP32: one pass casts
+    // at scale 1 and records the max-abs
     const bool single_pass =
-        (prec == F16 && t.scale_mode == 0) || (prec == F32 && !single_wg);
+        (prec == F16 && t.scale_mode != 1) || (prec == F32 && !single_wg);
     if (single_pass) with_parts = false;
     // Single pass: operands of the group with the same columns whose rows
     // overlap or touch share one scale-1 copy of the union of their rows (a

@@ -59,8 +59,9 @@ hipError_t launch_node_scales(int n_nodes, const StatJob* jobs, const double* pa
                               int scale_mode, double* scales, hipStream_t s);
 hipError_t launch_node_labels(const PNode* nodes, int n_nodes, const StatJob* xjobs,
                               const double* xparts, const StatJob* ajobs, const double* aparts,
-                              double tau, double sum_s2, double* err, int32_t* labels,
-                              hipStream_t s);
+                              double tau, const double* g, double sum_s2, double* err,
+                              int32_t* labels, hipStream_t s);
+hipError_t launch_pivot_ratio(const double* L, int64_t ldl, int64_t n, double* g, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t rows, const float* X, const float* params, float* probs,
                               int32_t* cls, hipStream_t s);
 hipError_t launch_mlp_grad(int64_t rows, const float* X, const int32_t* y, const float* params,

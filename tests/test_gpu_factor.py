@@ -73,11 +73,12 @@ def _trees(M):
         M.Tree(leaf=100, offdiag=[M.F16, M.F16, M.F32], split_align=32),
         M.Tree(leaf=256, offdiag=[M.F16, M.F32]),
         M.Tree(leaf=16, offdiag=[M.F16], syrk_leaf_mode=1),
+        M.Tree(leaf=32, offdiag=[M.E4M3, M.F16, M.F32], scale_mode=2),
     ]
 
 
 @pytest.mark.parametrize("n", [1, 7, 64, 130, 300])
-@pytest.mark.parametrize("ti", range(8))
+@pytest.mark.parametrize("ti", range(9))
 def test_integer_factor_bitwise(M, ctx, n, ti):
     """Substitution leaf TRSM: L0 bit for bit.  Inverse-based leaf TRSM (the
     default for FP64 leaves): L0 up to the rounding of the leaf inverses."""
@@ -198,6 +199,7 @@ MIXED = [
     ("[F16,F32] b256", 1024, 1.5, 0.0, dict(leaf=256, offdiag=[1, 2])),
     ("F16 leafSYRK64", 700, 1.1, 0.0, dict(leaf=64, offdiag=[1], syrk_leaf_mode=1)),
     ("E4M3/F16/F32 node", 640, 1.3, 0.0, dict(leaf=40, offdiag=[0, 1, 2], scale_mode=1)),
+    ("E4M3 up, F16 down", 640, 1.3, 0.0, dict(leaf=40, offdiag=[0, 1, 2], scale_mode=2)),
 ]
 
 
