@@ -29,7 +29,8 @@ FP64 reference of every step of it:
              and g >= 1 / kappa_2(A).  Refinement (Section 2.2) contracts by
              about kappa times the factor's relative error, so the budget
              shrinks with the conditioning that g indicates;
-  labels     the cheapest p (E4M3 < F16 < F32 < F64) with e(p) <= budget;
+  labels     the cheapest p (E4M3 < F16 < F32 < F64), not below a floor
+             min_prec, with e(p) <= budget;
   mlp        x_hat = (x - mu) / sigma, h1 = relu(W1 x_hat + b1),
              h2 = relu(W2 h1 + b2), z = W3 h2 + b3, p = softmax(z); mean
              cross-entropy loss; its exact gradient; one Adam step.
@@ -150,11 +151,12 @@ def budgets(n: int, leaf: int, align: int, tau: float, g: float = 1.0) -> np.nda
     return tau * g * s2 / s2.sum() if s2.size else s2
 
 
-def labels_from(err: np.ndarray, bud: np.ndarray) -> np.ndarray:
+def labels_from(err: np.ndarray, bud: np.ndarray, min_prec: int = E4M3) -> np.ndarray:
+    """Cheapest format from min_prec up whose error fits the node's budget."""
     lab = np.full(err.shape[0], F64, dtype=np.int64)
     for i in range(err.shape[0]):
         for p in (E4M3, F16, F32):
-            if err[i, p] <= bud[i]:
+            if p >= min_prec and err[i, p] <= bud[i]:
                 lab[i] = p
                 break
     return lab

@@ -117,6 +117,9 @@ def test_budgets_and_labels():
     err = np.array([[1e-9, 0, 0], [1e-3, 1e-6, 0], [1, 1, 1], [1e-3, 1e-3, 1e-12]])
     bud = np.array([1e-8, 1e-5, 1e-2, 1e-12])
     np.testing.assert_array_equal(P.labels_from(err, bud), [O.E4M3, O.F16, O.F64, O.F32])
+    # a floor: formats below it are never chosen, the rest of the rule unchanged
+    np.testing.assert_array_equal(P.labels_from(err, bud, O.F16), [O.F16, O.F16, O.F64, O.F32])
+    np.testing.assert_array_equal(P.labels_from(err, bud, O.F32), [O.F32, O.F32, O.F64, O.F32])
 
 
 def test_pivot_ratio_closed_form_and_definition():
