@@ -5,7 +5,7 @@ per-node choice is this project's addition on top of that fixed layering (the
 paper's future work, Section 5, names dynamic quantization instead).  The
 policy built here picks the precision of every internal Tree-POTRF node (the
 node's Tree-TRSM and Tree-SYRK updates, Algorithm 1) from five features of
-the input matrix, with a 5-64-64-4 perceptron.  This module is the plain
+the input matrix, with a 6-64-64-4 perceptron.  This module is the plain
 FP64 reference of every step of it:
 
   nodes      internal Tree-POTRF nodes in preorder (the numbering of the
@@ -17,6 +17,13 @@ FP64 reference of every step of it:
                f3 = log2( min over the node's rows i of a_ii / sum_{j != i} |a_ij| ),
                     full rows of the symmetric A, clamped to [-30, 30]
                f4 = depth,  f5 = log2(m1)
+               f6 = log2( min over the node's rows i of (a_ii - max_{j != i} |a_ij|)
+                          / mean diag of the node ), full rows, clamped to [-30, 30]
+                    (values <= 2^-30, including <= 0, give -30).  For equal diagonal
+                    entries a_ii - |a_ij| is the smaller eigenvalue of the 2 x 2
+                    principal submatrix (i, j), an upper bound on lambda_min(A) by
+                    interlacing: the one feature that sees a small lambda_min in a
+                    matrix that is not diagonally dominant.
   errors     per node and p in (E4M3, F16, F32), with X = L21 of an FP64
              factor (the operand block the node's updates multiply):
                e(p) = 2 ||X||_F ||X - s Q_p(X / s)||_F / ||A_node||_F,
@@ -47,8 +54,8 @@ from . import E4M3, F16, F32, F64, round_array, scale, split
 
 H = 64
 NCLS = 4
-NFEAT = 5
-# flat parameter layout: mu(5) sigma(5) W1(64x5) b1(64) W2(64x64) b2(64) W3(4x64) b3(4), row-major
+NFEAT = 6
+# flat parameter layout: mu(6) sigma(6) W1(64x6) b1(64) W2(64x64) b2(64) W3(4x64) b3(4), row-major
 SIZES = [("mu", (NFEAT,)), ("sigma", (NFEAT,)), ("W1", (H, NFEAT)), ("b1", (H,)),
          ("W2", (H, H)), ("b2", (H,)), ("W3", (NCLS, H)), ("b3", (NCLS,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SIZES)
@@ -94,6 +101,9 @@ def features(A: np.ndarray, n: int, leaf: int, align: int = 1) -> np.ndarray:
     off = np.abs(S).sum(axis=1) - np.abs(d)
     with np.errstate(divide="ignore", invalid="ignore"):
         ratio = np.where(off > 0, d / off, np.inf)
+    Soff = np.abs(S)
+    np.fill_diagonal(Soff, 0.0)
+    gap = d - Soff.max(axis=1) if n > 1 else d.copy()
     out = []
     for (i0, m, m1, dep) in nodes(n, leaf, align):
         X = S[i0 + m1:i0 + m, i0:i0 + m1]
@@ -109,7 +119,9 @@ def features(A: np.ndarray, n: int, leaf: int, align: int = 1) -> np.ndarray:
         f2 = math.log2(mx / rms) if rms > 0.0 else 0.0
         r = float(np.min(ratio[i0:i0 + m]))
         f3 = 30.0 if r >= 2.0 ** 30 else (-30.0 if r <= 2.0 ** -30 else math.log2(r))
-        out.append([f1, f2, f3, float(dep), math.log2(m1)])
+        v = float(np.min(gap[i0:i0 + m])) / mdiag
+        f6 = 30.0 if v >= 2.0 ** 30 else (-30.0 if v <= 2.0 ** -30 else math.log2(v))
+        out.append([f1, f2, f3, float(dep), math.log2(m1), f6])
     return np.array(out, dtype=np.float64).reshape(-1, NFEAT)
 
 

@@ -29,14 +29,17 @@ def test_features_compound_symmetry(n, leaf, a, beta):
     # every off-diagonal row sum (n - 1) |beta|
     F = P.features(_compound(n, a, beta), n, leaf)
     nd = P.nodes(n, leaf)
-    assert F.shape == (len(nd), 5)
+    assert F.shape == (len(nd), 6)
     f1 = math.log2(abs(beta) / math.sqrt(a + beta))
     f3 = math.log2((a + beta) / ((n - 1) * abs(beta)))
+    # every row: a_ii - max |a_ij| = a + beta - |beta|, over the mean diagonal a + beta
+    f6 = math.log2((a + beta - abs(beta)) / (a + beta))
     for row, (i0, m, m1, d) in zip(F, nd):
         assert row[0] == pytest.approx(f1, abs=1e-12)
         assert row[1] == pytest.approx(0.0, abs=1e-12)
         assert row[2] == pytest.approx(f3, abs=1e-12)
         assert row[3] == d and row[4] == math.log2(m1)
+        assert row[5] == pytest.approx(f6, abs=1e-12)
 
 
 def test_features_diagonal_and_single_entry():
@@ -44,6 +47,9 @@ def test_features_diagonal_and_single_entry():
     A = np.asfortranarray(np.diag(np.arange(1.0, n + 1)))
     F = P.features(A, n, 4)
     assert np.all(F[:, 0] == -64.0) and np.all(F[:, 1] == 0.0) and np.all(F[:, 2] == 30.0)
+    # f6 of a diagonal matrix: min diag / mean diag of the node (root: 1 / 8.5)
+    for row, (i0, m, m1, d) in zip(F, P.nodes(n, 4)):
+        assert row[5] == pytest.approx(math.log2((i0 + 1) / (i0 + (m + 1) / 2)), abs=1e-12)
     # one nonzero 0.5 in the root's A21 (rows 8..15, cols 0..7): 64 entries,
     # rms = 0.5 / 8, max / rms = 8; root mean diag = 8.5; row 9 ratio = 10 / 0.5
     A[9, 2] = A[2, 9] = 0.5
@@ -51,6 +57,15 @@ def test_features_diagonal_and_single_entry():
     assert F[0, 0] == pytest.approx(math.log2((0.5 / 8) / math.sqrt(8.5)), abs=1e-12)
     assert F[0, 1] == pytest.approx(3.0, abs=1e-12)
     assert F[0, 2] == pytest.approx(math.log2(3.0 / 0.5), abs=1e-12)   # row 2: a_22 = 3
+    # node [0, 8) holds row 2: a_22 - 0.5 = 2.5 > its min diag 1, so f6 keeps
+    # 1 / 4.5; a 2 x 2 block [[1, 0.9], [0.9, 1]] on rows 0, 1 brings the
+    # root's min gap to 0.1
+    assert F[1, 5] == pytest.approx(math.log2(1.0 / 4.5), abs=1e-12)
+    C = A.copy()
+    C[0, 0] = C[1, 1] = 1.0
+    C[1, 0] = C[0, 1] = 0.9
+    assert P.features(C, n, 4)[0, 5] == pytest.approx(math.log2(0.1 / ((1 + 1 + sum(range(3, 17))) / 16)),
+                                                      abs=1e-12)
     # the lower triangle alone decides: garbage above the diagonal is ignored
     B = A.copy()
     B[np.triu_indices(n, 1)] = 7.0
@@ -187,8 +202,8 @@ def _rand_params(seed):
     rng = np.random.default_rng(seed)
     p = rng.normal(0, 0.4, P.NPARAM)
     u = P.unpack(p)
-    u["mu"][:] = rng.normal(0, 1, 5)
-    u["sigma"][:] = rng.uniform(0.5, 2.0, 5)
+    u["mu"][:] = rng.normal(0, 1, P.NFEAT)
+    u["sigma"][:] = rng.uniform(0.5, 2.0, P.NFEAT)
     return p
 
 
@@ -196,14 +211,16 @@ def test_mlp_forward_hand():
     p = np.zeros(P.NPARAM)
     u = P.unpack(p)
     u["sigma"][:] = 1.0
-    prob, _ = P.forward(p, np.zeros((3, 5)))
+    prob, _ = P.forward(p, np.zeros((3, P.NFEAT)))
     np.testing.assert_allclose(prob, 0.25)
-    assert P.loss(p, np.zeros((3, 5)), np.array([0, 1, 3])) == pytest.approx(math.log(4))
+    assert P.loss(p, np.zeros((3, P.NFEAT)), np.array([0, 1, 3])) == pytest.approx(math.log(4))
     # one path: h1[0] = relu(x0), h2[0] = relu(2 h1[0]), z = [3 h2[0], 0, 0, 0]
     u["W1"][0, 0] = 1.0
     u["W2"][0, 0] = 2.0
     u["W3"][0, 0] = 3.0
-    prob, _ = P.forward(p, np.array([[0.5, 0, 0, 0, 0], [-1.0, 0, 0, 0, 0]]))
+    X = np.zeros((2, P.NFEAT))
+    X[:, 0] = [0.5, -1.0]
+    prob, _ = P.forward(p, X)
     e3 = math.exp(3.0)
     np.testing.assert_allclose(prob[0], [e3 / (e3 + 3), 1 / (e3 + 3), 1 / (e3 + 3), 1 / (e3 + 3)])
     np.testing.assert_allclose(prob[1], 0.25)
@@ -212,11 +229,13 @@ def test_mlp_forward_hand():
 def test_mlp_gradient_finite_differences():
     p = _rand_params(1)
     rng = np.random.default_rng(2)
-    X = rng.normal(0, 1.5, (40, 5))
+    X = rng.normal(0, 1.5, (40, P.NFEAT))
     y = rng.integers(0, 4, 40)
     _, g = P.loss_grad(p, X, y)
-    assert np.all(g[:10] == 0.0)
-    idx = np.concatenate([np.arange(10, 40), rng.choice(np.arange(40, P.NPARAM), 200, replace=False),
+    t0 = 2 * P.NFEAT                      # mu and sigma are not trained
+    assert np.all(g[:t0] == 0.0)
+    idx = np.concatenate([np.arange(t0, t0 + 30),
+                          rng.choice(np.arange(t0 + 30, P.NPARAM), 200, replace=False),
                           np.arange(P.NPARAM - 4, P.NPARAM)])
     h = 1e-6
     for i in idx:
@@ -236,7 +255,8 @@ def test_adam_first_step_is_signed_lr():
     v = np.zeros_like(p)
     q, m1, v1 = P.adam_step(p, g, m, v, 1, 1e-3, eps=0.0)
     # bias-corrected first step: m_hat = g, v_hat = g^2
-    np.testing.assert_allclose(q[10:], p[10:] - 1e-3 * np.sign(g[10:]), rtol=0, atol=1e-15)
-    np.testing.assert_array_equal(q[:10], p[:10])
-    np.testing.assert_allclose(m1[10:], 0.1 * g[10:])
-    np.testing.assert_allclose(v1[10:], 0.001 * g[10:] ** 2)
+    t0 = 2 * P.NFEAT
+    np.testing.assert_allclose(q[t0:], p[t0:] - 1e-3 * np.sign(g[t0:]), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(q[:t0], p[:t0])
+    np.testing.assert_allclose(m1[t0:], 0.1 * g[t0:])
+    np.testing.assert_allclose(v1[t0:], 0.001 * g[t0:] ** 2)
