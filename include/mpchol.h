@@ -72,8 +72,8 @@ enum {
  *                max|B| <= Rmax*s, and s >= 1 (Section 3.4 with alpha rounded
  *                up to a power of two); 1: also scale up (e < 0) for FP16 and
  *                E4M3 operands; 2: scale up E4M3 operands only (FP16 as in 0,
- *                so its casts stay single-pass).  FP32 operands are never
- *                scaled up.
+ *                so its casts stay single-pass; not supported by
+ *                mpchol_factor_batched).  FP32 operands are never scaled up.
  *   scale_tile   must be 0 (one scale per GEMM operand block).
  *   leaf_trsm    0: an FP64 leaf TRSM (Algorithm 2 base case) multiplies by
  *                the leaf's inverse, formed once per kernel leaf (FP64 MFMA,
@@ -180,7 +180,10 @@ int mpchol_solve(mpchol_ctx ctx, int64_t n, int64_t nrhs, const double* A, int64
 /*
  * mpchol_solve for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same solve and refinement, run on the same kernels, with every scratch
+ * same solve and refinement, run on the same kernels except the FP64
+ * residual (it reads each tile of A twice instead of once, since the
+ * single-read residual's partial sums would not fit the fixed array; the
+ * sums then differ in rounding order), with every scratch
  * buffer in a fixed device array that the library owns (one per GPU, held
  * until the process ends; about 29 MB: MPCHOL_NOALLOC_MAX_N x
  * MPCHOL_NOALLOC_MAX_RHS).  No context, no hipMalloc / hipFree / host pinning,
@@ -223,7 +226,8 @@ int mpchol_solve_noalloc(int device, int64_t n, int64_t nrhs, const double* A, i
  *   info_host   NULL or host array of batch mpchol_info (status, failed
  *               index, refinement steps, last correction; ms_factor = the
  *               whole launch).
- * Synchronizes the stream.  Returns the largest status code over the systems.
+ * Synchronizes the stream.  Returns the largest status code over the systems,
+ * or MPCHOL_NOT_SUPPORTED for scale_mode 2.
  * Errors: -2 batch < 0; -3 n_host / a size outside 1..2^20; -4 A_dev; -5 lda;
  * -6 L_dev (NULL, or equal to A_dev with nrhs > 0); -7 ldl; -8 nrhs; -9 B_dev / X_dev; -12 max_iter; -13 descriptor.
  */
@@ -329,28 +333,31 @@ int mpchol_backward_error(mpchol_ctx ctx, int64_t n, const double* A, int64_t ld
  * addition on top of that fixed layering (the paper's future work, Section 5,
  * names dynamic quantization instead).  Here each internal Tree-POTRF node (Algorithm 1;
  * order m > leaf, numbered in preorder like mpchol_tree.node_prec) gets the
- * precision of its Tree-TRSM / Tree-SYRK updates from a 5-64-64-4 perceptron
- * (ReLU, softmax over {E4M3, F16, F32, F64}) evaluated on five features of the
+ * precision of its Tree-TRSM / Tree-SYRK updates from a 6-64-64-4 perceptron
+ * (ReLU, softmax over {E4M3, F16, F32, F64}) evaluated on six features of the
  * input matrix, computed before the factorization so the plan stays static:
  *   f1 = log2(rms(A21) / sqrt(mean diagonal of the node))   (-64 if A21 = 0)
  *   f2 = log2(max|A21| / rms(A21))                          (0 if A21 = 0)
  *   f3 = log2(min over the node's rows i of a_ii / sum_{j!=i} |a_ij|), full
  *        rows of the symmetric A, clamped to [-30, 30]
  *   f4 = depth,  f5 = log2(m1)      (A21 = A[i0+m1 : i0+m, i0 : i0+m1])
- * Parameters: MPCHOL_MLP_PARAMS floats, mu(5) sigma(5) W1(64x5) b1(64)
+ *   f6 = log2(min over the node's rows i of (a_ii - max_{j!=i} |a_ij|) / mean
+ *        diagonal of the node), full rows, clamped to [-30, 30] (an upper
+ *        bound on lambda_min by 2x2 interlacing when the diagonal is constant)
+ * Parameters: MPCHOL_MLP_PARAMS floats, mu(6) sigma(6) W1(64x6) b1(64)
  * W2(64x64) b2(64) W3(4x64) b3(4), matrices row-major (out x in); the input
  * is standardized as (x - mu) / sigma.  All buffers below are device memory
  * unless named _host.
  * ------------------------------------------------------------------------ */
-#define MPCHOL_MLP_PARAMS 4814
+#define MPCHOL_MLP_PARAMS 4880
 
 /* Internal nodes of an order-n factorization under `tree` (host only).
  * table_host: NULL, or room for 4 int64 per node: i0, m, m1, depth.
  * Returns the node count, or a negative argument error (-1 n < 0; -2 tree). */
 int64_t mpchol_policy_nodes(int64_t n, const mpchol_tree* tree, int64_t* table_host);
 
-/* feat (nodes x 5 floats) <- the features of every node of A (lower
- * triangle, column-major, lda >= n).  Reads the lower triangle twice.
+/* feat (nodes x 6 floats) <- the features of every node of A (lower
+ * triangle, column-major, lda >= n).  Reads the lower triangle three times.
  * Asynchronous on `stream`.  Errors: -2 n; -3 A; -4 lda; -5 tree; -6 feat. */
 int mpchol_policy_features(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
                            const mpchol_tree* tree, float* feat, void* stream);
@@ -359,17 +366,18 @@ int mpchol_policy_features(mpchol_ctx ctx, int64_t n, const double* A, int64_t l
  * p in {E4M3, F16, F32}: e(p) = 2 ||X||_F ||X - s Q_p(X/s)||_F / ||A_node||_F
  * (s: the block's power-of-two scale under scale_mode, Section 3.4; A_node
  * the node's symmetric diagonal block); label = the cheapest p with
- * e(p) <= tau * g * m1_k^2 / sum_j m1_j^2, else F64, where g = min_i l_ii^2 /
+ * e(p) <= tau * g * m1_k^2 / sum_j m1_j^2 among p >= min_prec, else F64, where g = min_i l_ii^2 /
  * max_i l_ii^2 is L's pivot ratio (g >= 1 / kappa_2(A): the budget shrinks
  * with the conditioning, as refinement's contraction does, Section 2.2).
  * err: NULL or nodes x 3 doubles; labels: nodes int32.  Asynchronous.
  * Errors: -2 n; -3 A; -4 lda; -5 L; -6 ldl; -7 tree; -8 tau <= 0;
- * -9 scale_mode; -10 labels. */
+ * -9 scale_mode; -10 labels; -11 min_prec outside [E4M3, F64]. */
 int mpchol_policy_labels(mpchol_ctx ctx, int64_t n, const double* A, int64_t lda,
                          const double* L, int64_t ldl, const mpchol_tree* tree, double tau,
-                         int32_t scale_mode, double* err, int32_t* labels, void* stream);
+                         int32_t scale_mode, int32_t min_prec, double* err, int32_t* labels,
+                         void* stream);
 
-/* Forward pass on rows x 5 features X (row-major): probs (rows x 4, or
+/* Forward pass on rows x 6 features X (row-major): probs (rows x 4, or
  * NULL) and the argmax class (rows, or NULL).  FP32.  Asynchronous.
  * Errors: -2 rows < 0; -3 X; -4 params. */
 int mpchol_mlp_forward(mpchol_ctx ctx, int64_t rows, const float* X, const float* params,

@@ -58,6 +58,9 @@ struct mpchol_ctx_s {
   // factorization
   hipStream_t side = nullptr;
   hipEvent_t ev_in = nullptr, ev_copy = nullptr;
+  // lookahead: a Tree-SYRK tail on the side stream (ev_la_main: the caller's
+  // stream has reached it; ev_la_side: the side stream's work is done)
+  hipEvent_t ev_la_main = nullptr, ev_la_side = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
   // per-launch-class event timing (mpchol_profile)
   uint32_t prof_mask = 0;
@@ -215,6 +218,17 @@ static int ensure_ws(mpchol_ctx c, size_t bytes, int64_t parts) {
   return 0;
 }
 
+// Lookahead mode of the single-matrix factorization (build_plan): 2 unless
+// MPCHOL_LOOKAHEAD says 0 or 1 (the switch that measures what the overlap
+// gains).
+static int lookahead_on() {
+  static const int mode = [] {
+    const char* e = getenv("MPCHOL_LOOKAHEAD");
+    return e && (e[0] == '0' || e[0] == '1') ? e[0] - '0' : 2;
+  }();
+  return mode;
+}
+
 // op 0: Tree-POTRF of order n; 1: Tree-TRSM of an n x k block against a k x k
 // factor; 2: Tree-SYRK of order n with k columns.
 static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, Plan** out,
@@ -229,7 +243,7 @@ static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, 
   std::unique_ptr<Plan> P(new Plan());
   if (op == 1) build_trsm_plan(*P, n, k, ldl, t);
   else if (op == 2) build_syrk_plan(*P, n, k, ldl, t);
-  else build_plan(*P, n, ldl, t);
+  else build_plan(*P, n, ldl, t, false, 0, lookahead_on());
   if (upload(&P->d_maxabs, P->maxabs) || upload(&P->d_casts, P->casts) ||
       upload(&P->d_gemms, P->gemms)) {
     free_plan(*P);
@@ -243,54 +257,67 @@ static int get_plan(mpchol_ctx c, int64_t n, int64_t ldl, const mpchol_tree* t, 
 // wait_at >= 0: the stream waits for wait_ev before launch wait_at.
 static int run_plan(mpchol_ctx c, const Plan& P, double* L, int64_t ldl, hipStream_t s,
                     int wait_at = -1, hipEvent_t wait_ev = nullptr) {
-  const int sm = P.tree.scale_mode;
   for (size_t li = 0; li < P.launches.size(); li++) {
     const Launch& Lc = P.launches[li];
+    const int sm = operand_scale_mode(P.tree.scale_mode, Lc.prec);
     if ((int)li == wait_at) HIPCHK(hipStreamWaitEvent(s, wait_ev, 0));
+    if (Lc.wait_side) HIPCHK(hipStreamWaitEvent(s, c->ev_la_side, 0));
+    hipStream_t ls = s;
+    if (Lc.side) {
+      // a lookahead tail: starts once the caller's stream has issued
+      // everything before it (the casts it reads)
+      HIPCHK(hipEventRecord(c->ev_la_main, s));
+      HIPCHK(hipStreamWaitEvent(c->side, c->ev_la_main, 0));
+      ls = c->side;
+    }
     hipError_t e = hipSuccess;
-    const int pk = c->prof_mask ? prof_begin(c, launch_kind(Lc), launch_work(P, Lc), s) : -1;
+    const int pk = c->prof_mask ? prof_begin(c, launch_kind(Lc), launch_work(P, Lc), ls) : -1;
     switch (Lc.kind) {
       case Launch::POTRF:
         if (Lc.a2 == 1)
           e = launch_potrf_inv(L, ldl, Lc.a0, (int)Lc.a1, c->dst,
-                               c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
+                               c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, ls);
         else
-          e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, s);
+          e = launch_potrf_leaf(Lc.prec, L, ldl, Lc.a0, (int)Lc.a1, c->dst, ls);
         break;
       case Launch::TRSM:
         if (Lc.first >= 0)
           e = launch_trsm_inv(L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3,
-                              c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
+                              c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, ls);
         else
-          e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, s);
+          e = launch_trsm_leaf(Lc.prec, L, ldl, Lc.a0, Lc.a1, Lc.a2, (int)Lc.a3, ls);
         break;
       case Launch::TRINV:
         e = launch_trinv(L, ldl, Lc.a0, (int)Lc.a1,
-                         c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, s);
+                         c->inv + (size_t)Lc.first * kInvLd * kInvLd + Lc.off, kInvLd, ls);
         break;
       case Launch::INVJOIN:
         e = launch_inv_join(L, ldl, Lc.a0, (int)Lc.a1, (int)Lc.a2,
-                            c->inv + (size_t)Lc.first * kInvLd * kInvLd, kInvLd, s);
+                            c->inv + (size_t)Lc.first * kInvLd * kInvLd, kInvLd, ls);
         break;
       case Launch::MAXABS:
-        e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, s);
+        e = launch_maxabs(L, ldl, P.d_maxabs + Lc.first, Lc.count, Lc.total, c->part, ls);
         break;
       case Launch::CAST:
         if (Lc.a0 == 1)
           e = launch_cast_max(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec,
-                              c->ws, s);
+                              c->ws, ls);
         else
           e = launch_cast(L, ldl, P.d_casts + Lc.first, Lc.count, Lc.total, c->part, Lc.prec, sm,
-                          c->ws, c->dst, s);
+                          c->ws, c->dst, ls);
         break;
       case Launch::GEMM:
         e = launch_gemm(Lc.prec, Lc.tile, L, ldl, c->ws, P.d_gemms + Lc.first, Lc.count,
-                        Lc.total, c->part, sm, c->dst, s);
+                        Lc.total, c->part, sm, c->dst, ls);
         break;
     }
-    prof_end(c, pk, s);
+    prof_end(c, pk, ls);
     if (e != hipSuccess) return MPCHOL_HIP_ERROR;
+    if (Lc.side) HIPCHK(hipEventRecord(c->ev_la_side, c->side));
   }
+  // every tail is joined by a later launch; joined again here so that the
+  // caller's stream never runs ahead of side-stream work
+  if (P.n_side > 0) HIPCHK(hipStreamWaitEvent(s, c->ev_la_side, 0));
   return 0;
 }
 
@@ -384,14 +411,19 @@ static int policy_features(mpchol_ctx c, int64_t n, const double* A, int64_t lda
   double* colsum = (double*)pol_buf(c, 1, sizeof(double) * (size_t)n);
   double* ratio = (double*)pol_buf(c, 2, sizeof(double) * (size_t)n);
   double* dparts = (double*)pol_buf(c, 3, sizeof(double) * 4 * (size_t)parts);
-  if (!rowpart || !colsum || !ratio || !dparts) return MPCHOL_HIP_ERROR;
+  double* rowmax = (double*)pol_buf(c, 19, sizeof(double) * (size_t)(nstrip * n));
+  double* colmax = (double*)pol_buf(c, 20, sizeof(double) * (size_t)n);
+  double* gap = (double*)pol_buf(c, 21, sizeof(double) * (size_t)n);
+  if (!rowpart || !colsum || !ratio || !dparts || !rowmax || !colmax || !gap)
+    return MPCHOL_HIP_ERROR;
   PNode* dn = nullptr;
   StatJob* dj = nullptr;
   if (upload_async(c, 4, T.nodes, &dn, s) || upload_async(c, 5, jobs, &dj, s)) return MPCHOL_HIP_ERROR;
-  HIPCHK(launch_rowabs(A, lda, n, rowpart, colsum, s));
-  HIPCHK(launch_row_ratio(A, lda, n, rowpart, colsum, ratio, s));
+  HIPCHK(launch_rowabs(A, lda, n, rowpart, colsum, 0, s));
+  HIPCHK(launch_rowabs(A, lda, n, rowmax, colmax, 1, s));
+  HIPCHK(launch_row_ratio(A, lda, n, rowpart, colsum, rowmax, colmax, ratio, gap, s));
   HIPCHK(launch_stats(A, lda, dj, (int)jobs.size(), parts, nullptr, dparts, s));
-  HIPCHK(launch_node_features(dn, nn, A, lda, dj, dparts, ratio, feat, s));
+  HIPCHK(launch_node_features(dn, nn, A, lda, dj, dparts, ratio, gap, feat, s));
   return 0;
 }
 
@@ -450,6 +482,8 @@ int64_t mpchol_policy_nodes(int64_t n, const mpchol_tree* tree, int64_t* table) 
   return (int64_t)rec.size();
 }
 
+static_assert(kMlpParams == MPCHOL_MLP_PARAMS, "perceptron layout of the header");
+
 int mpchol_policy_features(mpchol_ctx c, int64_t n, const double* A, int64_t lda,
                            const mpchol_tree* tree, float* feat, void* stream) {
   if (!c) return -1;
@@ -466,7 +500,7 @@ int mpchol_policy_features(mpchol_ctx c, int64_t n, const double* A, int64_t lda
 
 int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, const double* L,
                          int64_t ldl, const mpchol_tree* tree, double tau, int32_t scale_mode,
-                         double* err, int32_t* labels, void* stream) {
+                         int32_t min_prec, double* err, int32_t* labels, void* stream) {
   if (!c) return -1;
   if (n < 0 || n > (int64_t)1 << 31) return -2;
   if (n > 0 && !A) return -3;
@@ -479,8 +513,9 @@ int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, 
   PolicyTables T;
   policy_tables(n, tree, T);
   const int nn = (int)T.nodes.size();
+  if (nn > 0 && !labels) return -10;
+  if (min_prec < MPCHOL_E4M3 || min_prec > MPCHOL_F64) return -11;
   if (nn == 0) return 0;
-  if (!labels) return -10;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->device));
   std::vector<StatJob> xj, xj2, aj;
@@ -504,11 +539,12 @@ int mpchol_policy_labels(mpchol_ctx c, int64_t n, const double* A, int64_t lda, 
       upload_async(c, 10, xj2, &dxj2, s) || upload_async(c, 11, aj, &daj, s))
     return MPCHOL_HIP_ERROR;
   HIPCHK(launch_stats(L, ldl, dxj, nn, xparts, nullptr, dx, s));
-  HIPCHK(launch_node_scales(nn, dxj, dx, scale_mode, sc, s));
+  HIPCHK(launch_node_scales(nn, dxj, dx, scale_mode, sc, s));   // mode 2 resolved per format
   HIPCHK(launch_stats(L, ldl, dxj2, nn, xparts2, sc, dx, s));
   HIPCHK(launch_stats(A, lda, daj, nn, aparts, nullptr, da, s));
   HIPCHK(launch_pivot_ratio(L, ldl, n, gd, s));
-  HIPCHK(launch_node_labels(dn, nn, dxj2, dx, daj, da, tau, gd, sum_s2, err, labels, s));
+  HIPCHK(launch_node_labels(dn, nn, dxj2, dx, daj, da, tau, gd, sum_s2, min_prec, err, labels,
+                            s));
   return 0;
 }
 
@@ -591,6 +627,8 @@ int mpchol_create(mpchol_ctx* ctx, int device) {
   HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_la_main, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_la_side, hipEventDisableTiming));
   *ctx = c.release();
   return 0;
 }
@@ -615,6 +653,8 @@ int mpchol_destroy(mpchol_ctx c) {
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+  if (c->ev_la_main) (void)hipEventDestroy(c->ev_la_main);
+  if (c->ev_la_side) (void)hipEventDestroy(c->ev_la_side);
   if (c->side) (void)hipStreamDestroy(c->side);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   free_batch(c);
@@ -1000,6 +1040,7 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
   if (max_iter < 0) return -12;
   int v = validate_tree(tree);
   if (v) return v == -7 ? -13 : v;
+  if (tree->scale_mode == 2) return MPCHOL_NOT_SUPPORTED;   // one block-scale mode per batch
   for (int64_t i = 0; i < batch; i++) {
     if (n_host[i] < 1 || n_host[i] > (1 << 20)) return -3;
     if (!A_dev[i] || !L_dev[i]) return -4;
@@ -1145,7 +1186,7 @@ int mpchol_factor_batched(mpchol_ctx c, int64_t batch, const int64_t* n_host,
     G.batch = (int32_t)batch;
     G.nrhs = (int32_t)nrhs;
     G.max_iter = max_iter;
-    G.scale_mode = tree->scale_mode;
+    G.scale_mode = tree->scale_mode;   // 0 or 1 (2 is rejected above)
     G.tol = tol;
     HIPCHK(hipHostMalloc((void**)&BT.hinfo, sizeof(BatchInfo) * (size_t)batch,
                          hipHostMallocDefault));
@@ -1215,6 +1256,7 @@ int mpchol_quantize(mpchol_ctx c, int64_t rows, int64_t cols, const double* src,
   if (!dst && rows > 0) return -8;
   if (ldq < ((cols + 15) / 16) * 16) return -9;
   if (rows > INT32_MAX || cols > INT32_MAX || ldq > INT32_MAX) return -2;
+  scale_mode = operand_scale_mode(scale_mode, prec);
   if (rows == 0 || cols == 0) {
     if (scale_out) *scale_out = 1.0;
     return 0;
@@ -1299,7 +1341,7 @@ int mpchol_plan_stats(int64_t n, int64_t ldl, const mpchol_tree* tree, double* f
   int v = validate_tree(tree);
   if (v) return v;
   Plan P;
-  build_plan(P, n, ldl, tree);
+  build_plan(P, n, ldl, tree, false, 0, lookahead_on());
   for (int i = 0; i < 4; i++) flops4[i] = P.stats.flops[i];
   *leaf_flops = P.stats.leaf_flops;
   *cast_bytes = P.stats.cast_bytes;

@@ -2,7 +2,7 @@
 // internal Tree-POTRF node (one pass over the lower triangle for the row
 // dominance ratios, one over the nodes' A21 blocks), the training labels
 // (quantization error of each node's L21 block against its share of the
-// error budget), and the 5-64-64-4 perceptron: forward pass, cross-entropy
+// error budget), and the 6-64-64-4 perceptron: forward pass, cross-entropy
 // gradient and Adam update, all in FP32 with fixed-order reductions, so that
 // every result is deterministic.
 #include "numfmt.h"
@@ -21,9 +21,13 @@ __device__ inline double dmax_fin(double m, double a) {
 }
 
 // ---------------------------------------------------------------- row sums
-// Strip b holds columns [64 b, 64 b + 64).  rowpart[b][i] = sum over the
-// strip's columns j < i of |A(i, j)| (rows i >= 64 b); colsum[j] = sum over
-// rows i > j of |A(i, j)|.  Lanes run along rows (coalesced).
+// Strip b holds columns [64 b, 64 b + 64).  rowpart[b][i] = sum (kMax: max)
+// over the strip's columns j < i of |A(i, j)| (rows i >= 64 b); colsum[j] =
+// sum (max) over rows i > j of |A(i, j)|.  Lanes run along rows (coalesced).
+template <bool kMax>
+__device__ inline double racc(double s, double a) { return kMax ? fmax(s, a) : s + a; }
+
+template <bool kMax>
 __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ A, int64_t lda, int64_t n,
                                                 double* __restrict__ rowpart,
                                                 double* __restrict__ colsum) {
@@ -40,8 +44,8 @@ __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ A, in
     for (int q = 0; q < 64; q++) {
       if (q < nc && c0 + q < i) {
         const double a = fabs(A[i + (c0 + q) * lda]);
-        rs += a;
-        cacc[q] += a;
+        rs = racc<kMax>(rs, a);
+        cacc[q] = racc<kMax>(cacc[q], a);
       }
     }
     rowpart[(int64_t)blockIdx.x * n + i] = rs;
@@ -51,23 +55,31 @@ __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ A, in
   for (int q = 0; q < 64; q++) {
     double v = cacc[q];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) v = racc<kMax>(v, __shfl_xor(v, off, 64));
     if (lane == q) red[wave][q] = v;
   }
   __syncthreads();
-  if (tid < nc) colsum[c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  if (tid < nc)
+    colsum[c0 + tid] = racc<kMax>(racc<kMax>(red[0][tid], red[1][tid]),
+                                  racc<kMax>(red[2][tid], red[3][tid]));
 }
 
-// ratio[i] = a_ii / sum_{j != i} |a_ij| (Inf when the row has no off-diagonal mass)
+// ratio[i] = a_ii / sum_{j != i} |a_ij| (Inf when the row has no off-diagonal
+// mass); gap[i] = a_ii - max_{j != i} |a_ij|
 __global__ void k_row_ratio(const double* __restrict__ A, int64_t lda, int64_t n,
                             const double* __restrict__ rowpart, const double* __restrict__ colsum,
-                            double* __restrict__ ratio) {
+                            const double* __restrict__ rowmax, const double* __restrict__ colmax,
+                            double* __restrict__ ratio, double* __restrict__ gap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = colsum[i];
-  for (int64_t b = 0; b <= i / 64; b++) s += rowpart[b * n + i];
+  double s = colsum[i], mx = colmax[i];
+  for (int64_t b = 0; b <= i / 64; b++) {
+    s += rowpart[b * n + i];
+    mx = fmax(mx, rowmax[b * n + i]);
+  }
   const double d = A[i + i * lda];
   ratio[i] = s > 0.0 ? d / s : kInf;
+  gap[i] = d - mx;
 }
 
 // ---------------------------------------------------------------- block stats
@@ -135,24 +147,28 @@ __global__ __launch_bounds__(256) void k_node_features(const PNode* __restrict__
                                                        const StatJob* __restrict__ jobs,
                                                        const double* __restrict__ parts,
                                                        const double* __restrict__ ratio,
+                                                       const double* __restrict__ gap,
                                                        float* __restrict__ feat) {
-  __shared__ double rsum[256], rmin[256];
+  __shared__ double rsum[256], rmin[256], gmin[256];
   const PNode N = nodes[blockIdx.x];
   const StatJob J = jobs[blockIdx.x];
   const int tid = threadIdx.x;
-  double ds = 0.0, mn = kInf;
+  double ds = 0.0, mn = kInf, gm = kInf;
   for (int i = tid; i < N.m; i += 256) {
     const int64_t g = N.i0 + i;
     ds += A[g + g * lda];
     mn = fmin(mn, ratio[g]);
+    gm = fmin(gm, gap[g]);
   }
   rsum[tid] = ds;
   rmin[tid] = mn;
+  gmin[tid] = gm;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) {
       rsum[tid] += rsum[tid + h];
       rmin[tid] = fmin(rmin[tid], rmin[tid + h]);
+      gmin[tid] = fmin(gmin[tid], gmin[tid + h]);
     }
     __syncthreads();
   }
@@ -178,6 +194,8 @@ __global__ __launch_bounds__(256) void k_node_features(const PNode* __restrict__
     f[2] = (float)f3;
     f[3] = (float)N.depth;
     f[4] = (float)log2((double)N.m1);
+    const double v = gmin[0] / mdiag;
+    f[5] = (float)(v >= 1073741824.0 ? 30.0 : (v <= 1.0 / 1073741824.0 ? -30.0 : log2(v)));
   }
 }
 
@@ -190,7 +208,9 @@ __global__ void k_node_scales(int n_nodes, const StatJob* __restrict__ jobs,
   const StatJob J = jobs[k];
   double mx = 0.0;
   for (int p = 0; p < J.nparts; p++) mx = fmax(mx, parts[(int64_t)(J.part0 + p) * 4 + 1]);
-  for (int p = 0; p < 3; p++) scales[k * 3 + p] = block_scale(mx, p, scale_mode);
+  // scale_mode 2: E4M3 scaled both ways (mode 1), FP16 / FP32 only down (mode 0)
+  for (int p = 0; p < 3; p++)
+    scales[k * 3 + p] = block_scale(mx, p, scale_mode == 2 ? (p == 0 ? 1 : 0) : scale_mode);
 }
 
 // g <- min_i l_ii^2 / max_i l_ii^2 over the diagonal of the factor L (one
@@ -222,7 +242,8 @@ __global__ void k_node_labels(const PNode* __restrict__ nodes, int n_nodes,
                               const StatJob* __restrict__ xjobs, const double* __restrict__ xparts,
                               const StatJob* __restrict__ ajobs, const double* __restrict__ aparts,
                               double tau, const double* __restrict__ g, double sum_s2,
-                              double* __restrict__ err, int32_t* __restrict__ labels) {
+                              int min_prec, double* __restrict__ err,
+                              int32_t* __restrict__ labels) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_nodes) return;
   const StatJob X = xjobs[k], Aj = ajobs[k];
@@ -242,7 +263,7 @@ __global__ void k_node_labels(const PNode* __restrict__ nodes, int n_nodes,
   for (int p = 2; p >= 0; p--) {
     const double ep = an > 0.0 ? 2.0 * xn * sqrt(e[p]) / an : kInf;
     if (err) err[k * 3 + p] = ep;
-    if (ep <= budget) lab = p;
+    if (p >= min_prec && ep <= budget) lab = p;
   }
   labels[k] = lab;
 }
@@ -461,18 +482,23 @@ __global__ void k_mlp_adam(int nwg, int64_t rows, const float* __restrict__ gpar
 }  // namespace
 
 hipError_t launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowpart,
-                         double* colsum, hipStream_t s) {
+                         double* colsum, int use_max, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rowabs, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, A, lda, n,
-                     rowpart, colsum);
+  if (use_max)
+    hipLaunchKernelGGL(k_rowabs<true>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, A, lda, n,
+                       rowpart, colsum);
+  else
+    hipLaunchKernelGGL(k_rowabs<false>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, A, lda,
+                       n, rowpart, colsum);
   return hipGetLastError();
 }
 
 hipError_t launch_row_ratio(const double* A, int64_t lda, int64_t n, const double* rowpart,
-                            const double* colsum, double* ratio, hipStream_t s) {
+                            const double* colsum, const double* rowmax, const double* colmax,
+                            double* ratio, double* gap, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_ratio, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, lda, n,
-                     rowpart, colsum, ratio);
+                     rowpart, colsum, rowmax, colmax, ratio, gap);
   return hipGetLastError();
 }
 
@@ -486,10 +512,10 @@ hipError_t launch_stats(const double* M, int64_t ld, const StatJob* jobs, int nj
 
 hipError_t launch_node_features(const PNode* nodes, int n_nodes, const double* A, int64_t lda,
                                 const StatJob* jobs, const double* parts, const double* ratio,
-                                float* feat, hipStream_t s) {
+                                const double* gap, float* feat, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_node_features, dim3((unsigned)n_nodes), dim3(256), 0, s, nodes, A, lda,
-                     jobs, parts, ratio, feat);
+                     jobs, parts, ratio, gap, feat);
   return hipGetLastError();
 }
 
@@ -503,11 +529,12 @@ hipError_t launch_node_scales(int n_nodes, const StatJob* jobs, const double* pa
 
 hipError_t launch_node_labels(const PNode* nodes, int n_nodes, const StatJob* xjobs,
                               const double* xparts, const StatJob* ajobs, const double* aparts,
-                              double tau, const double* g, double sum_s2, double* err,
-                              int32_t* labels, hipStream_t s) {
+                              double tau, const double* g, double sum_s2, int min_prec,
+                              double* err, int32_t* labels, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_node_labels, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s,
-                     nodes, n_nodes, xjobs, xparts, ajobs, aparts, tau, g, sum_s2, err, labels);
+                     nodes, n_nodes, xjobs, xparts, ajobs, aparts, tau, g, sum_s2, min_prec, err,
+                     labels);
   return hipGetLastError();
 }
 

@@ -851,7 +851,7 @@ __global__ __launch_bounds__(256, 1) void k_resid4(const double* __restrict__ A,
   f64x4_t accT = {0.0, 0.0, 0.0, 0.0};
   const int orow = 16 * wv + (l >> 4), ocol = l & 15;
   auto step = [&](int t, double (&f)[16], double (&tr)[16], double (&pf)[16], double (&ptr)[16]) {
-    if (t + 2 < T) {
+    if (t + 3 < T) {
       issue(ahead, pf, ptr);
       adv(ahead);
     }
@@ -885,21 +885,28 @@ __global__ __launch_bounds__(256, 1) void k_resid4(const double* __restrict__ A,
     }
     adv(cur);
   };
-  double fa[16], ta[16], fb[16], tb[16], fc[16], tc[16];
+  // four register sets: tiles t + 1 .. t + 3 in flight while tile t computes
+  double fa[16], ta[16], fb[16], tb[16], fc[16], tc[16], fd[16], td[16];
   issue(ahead, fa, ta);
   adv(ahead);
   if (T > 1) {
     issue(ahead, fb, tb);
     adv(ahead);
   }
+  if (T > 2) {
+    issue(ahead, fc, tc);
+    adv(ahead);
+  }
   int t = 0;
-  for (; t + 2 < T; t += 3) {
-    step(t, fa, ta, fc, tc);
+  for (; t + 3 < T; t += 4) {
+    step(t, fa, ta, fd, td);
     step(t + 1, fb, tb, fa, ta);
     step(t + 2, fc, tc, fb, tb);
+    step(t + 3, fd, td, fc, tc);
   }
-  if (t < T) step(t, fa, ta, fc, tc);
+  if (t < T) step(t, fa, ta, fd, td);
   if (t + 1 < T) step(t + 1, fb, tb, fa, ta);
+  if (t + 2 < T) step(t + 2, fc, tc, fb, tb);
   // forward sums of the super-row (rows past n land in slots nobody reads)
   double* dst = part + ((int64_t)P * nsup + Q) * SR * MAXRHS;
   for (int ii = 0; ii < nI; ii++)

@@ -106,8 +106,7 @@ __device__ inline uint32_t encode_bits(double x, int prec) {
 }
 
 // Block scale: the smallest power of two s = 2^e with maxabs <= Rmax * s;
-// e >= 0 in scale_mode 0, for FP32, and for FP16 in scale_mode 2 (which
-// scales only E4M3 up).  maxabs = 0 or non-finite -> 1.
+// e >= 0 in scale_mode 0 and for FP32.  maxabs = 0 or non-finite -> 1.
 __host__ __device__ inline double block_scale(double maxabs, int prec, int scale_mode) {
   if (prec == 3) return 1.0;
   if (!(maxabs > 0.0) || maxabs > 1.7976931348623157e308) return 1.0;
@@ -120,7 +119,7 @@ __host__ __device__ inline double block_scale(double maxabs, int prec, int scale
   e = em - er - 1;
   while (maxabs > ldexp(R, e)) e++;
   while (maxabs <= ldexp(R, e - 1)) e--;
-  if ((scale_mode == 0 || prec == 2 || (scale_mode == 2 && prec != 0)) && e < 0) e = 0;
+  if ((scale_mode == 0 || prec == 2) && e < 0) e = 0;
   return ldexp(1.0, e);
 }
 

@@ -83,6 +83,15 @@ struct Builder {
   int64_t next_node = 0;
   size_t ws_cursor = 0;   // bytes used by the current group of quantized copies
   int64_t part_cursor = 0;
+  // lookahead: groups whose copies and partials go to bank 1 (offset past
+  // bank 0's high-water marks once the plan is complete)
+  int lookahead = 0;   // 0 off; 1 every Tree-SYRK; 2 only FP32 / FP64 ones
+  bool tail_pending = false;
+  int bank = 0;
+  size_t ws_max[2] = {0, 0};
+  int64_t parts_max[2] = {0, 0};
+  struct BankRange { size_t mj0, mj1, cj0, cj1, gp0, gp1; int esz; bool quant; };
+  std::vector<BankRange> bank1;
 
   Builder(Plan& p, const mpchol_tree& tr, int64_t ld) : P(p), t(tr), ldl(ld) {}
 
@@ -98,8 +107,35 @@ struct Builder {
     part_cursor = 0;
   }
   void end_group() {
+    ws_max[bank] = std::max(ws_max[bank], ws_cursor);
+    parts_max[bank] = std::max(parts_max[bank], part_cursor);
     P.ws_bytes = std::max(P.ws_bytes, ws_cursor);
     P.parts = std::max(P.parts, part_cursor);
+  }
+
+  // Bank 1 after bank 0: shift the offsets of every bank-1 group.
+  void place_banks() {
+    if (bank1.empty()) return;
+    const size_t ws0 = (size_t)rup((int64_t)ws_max[0], 256);
+    const int64_t p0 = parts_max[0];
+    for (const BankRange& r : bank1) {
+      for (size_t i = r.mj0; i < r.mj1; i++) P.maxabs[i].part0 += (int)p0;
+      for (size_t i = r.cj0; i < r.cj1; i++) {
+        P.casts[i].dst += (int64_t)(ws0 / r.esz);
+        P.casts[i].part0 += (int)p0;
+      }
+      for (size_t i = r.gp0; i < r.gp1; i++) {
+        GemmProb& g = P.gemms[i];
+        if (r.quant) {
+          g.x += (int64_t)(ws0 / r.esz);
+          g.y += (int64_t)(ws0 / r.esz);
+        }
+        if (g.xnparts > 0) g.xpart0 += (int)p0;
+        if (g.ynparts > 0) g.ypart0 += (int)p0;
+      }
+    }
+    P.ws_bytes = ws0 + ws_max[1];
+    P.parts = p0 + parts_max[1];
   }
 
   // Max-abs job for block (r, c, rows, cols); returns (part0, nparts).
@@ -152,9 +188,15 @@ struct Builder {
 
   // Emit maxabs / cast / grouped GEMM launches for independent GEMM nodes that
   // share one precision.
-  void emit_group(const std::vector<Node>& nodes, int prec, bool with_parts) {
+  // head_count >= 0: the first head_count nodes form the GEMM launch of the
+  // caller's stream and the rest a launch on the side stream, issued first
+  // (after the casts both read), with the group's copies in bank 1.
+  void emit_group(const std::vector<Node>& nodes, int prec, bool with_parts,
+                  int head_count = -1) {
     if (nodes.empty()) return;
     begin_group();
+    const size_t mj_first = P.maxabs.size(), cj_first = P.casts.size(),
+                 gp_first = P.gemms.size();
     std::vector<MaxabsJob> mj;
     std::vector<CastJob> cj;
     std::vector<GemmProb> gp;
@@ -363,13 +405,16 @@ struct Builder {
       P.casts.insert(P.casts.end(), cj.begin(), cj.end());
       P.launches.push_back(L);
     }
-    {
+    // GEMM launch over the problems [g0, g1) of gp (side: on the side stream)
+    auto gemm_launch = [&](size_t g0, size_t g1, int side) {
       Launch L{Launch::GEMM, prec};
+      L.side = side;
       L.first = (int)P.gemms.size();
-      L.count = (int)gp.size();
+      L.count = (int)(g1 - g0);
+      std::vector<GemmProb> sub(gp.begin() + g0, gp.begin() + g1);
       auto tiles_of = [&](int T) {
         int64_t tot = 0;
-        for (auto& g : gp) {
+        for (auto& g : sub) {
           int64_t tm = cdiv(g.m, T);
           tot += g.lower ? tm * (tm + 1) / 2 : tm * cdiv(g.n, T);
         }
@@ -379,7 +424,7 @@ struct Builder {
         L.tile = tile_force;
       } else if (single_wg) {
         int mn = 1 << 30;
-        for (auto& g : gp) mn = std::min(mn, std::min(g.m, g.n));
+        for (auto& g : sub) mn = std::min(mn, std::min(g.m, g.n));
         L.tile = mn >= 128 ? 128 : 64;
       } else {
         // 128 x 128 tiles unless that leaves most of the 256 CUs idle; FP32 /
@@ -391,24 +436,36 @@ struct Builder {
         if (L.tile == 64 && (prec == F32 || prec == F64) && tiles_of(64) < 256) L.tile = 32;
         if (prec == F16 && tiles_of(256) >= 256) {
           bool ok = true;
-          for (auto& g : gp)
+          for (auto& g : sub)
             ok = ok && g.k % 64 == 0 && (int64_t)g.m * g.ldx * 2 < ((int64_t)1 << 31) &&
                  (int64_t)g.n * g.ldy * 2 < ((int64_t)1 << 31);
           if (ok) L.tile = 256;
         }
       }
       int tiles = 0;
-      for (auto& g : gp) {
+      for (auto& g : sub) {
         g.tiles_m = (int)cdiv(g.m, L.tile);
         g.tiles_n = (int)cdiv(g.n, L.tile);
         g.tile_start = tiles;
         tiles += g.lower ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
       }
       L.total = tiles;
-      P.gemms.insert(P.gemms.end(), gp.begin(), gp.end());
+      P.gemms.insert(P.gemms.end(), sub.begin(), sub.end());
       P.launches.push_back(L);
+      if (side) P.n_side++;
+    };
+    if (head_count >= 0 && head_count < (int)gp.size()) {
+      gemm_launch((size_t)head_count, gp.size(), 1);
+      if (head_count > 0) gemm_launch(0, (size_t)head_count, 0);
+    } else {
+      gemm_launch(0, gp.size(), 0);
     }
     end_group();
+    if (bank == 1) {
+      const int esz = prec == F32 ? 4 : prec == F16 ? 2 : 1;
+      bank1.push_back({mj_first, P.maxabs.size(), cj_first, P.casts.size(), gp_first,
+                       P.gemms.size(), esz, quant});
+    }
   }
 
   void gemm_one(const Node& nd, bool with_parts) { emit_group({nd}, nd.prec, with_parts); }
@@ -513,9 +570,29 @@ struct Builder {
     syrk_collect(c0 + s1, s2, p0, K, prec, out);
   }
 
-  void syrk(int64_t c0, int64_t s, int64_t p0, int64_t K, int prec) {
-    if (s <= 0 || K <= 0) return;
+  // Returns true when the Tree-SYRK was split for lookahead (its tail is then
+  // in flight on the side stream).
+  bool syrk(int64_t c0, int64_t s, int64_t p0, int64_t K, int prec, bool split = false) {
+    if (s <= 0 || K <= 0) return false;
     std::vector<Node> all;
+    if (split && s > t.leaf) {
+      // head: the leading block [c0, c0 + s1) that Tree-POTRF of this block
+      // factors first; tail: the block below it and the trailing block
+      const int64_t s1 = split_rule(s, t.split_align), s2 = s - s1;
+      syrk_collect(c0, s1, p0, K, prec, all);
+      const int head = (int)all.size();
+      all.push_back(Node{c0 + s1, c0, (int)s2, (int)s1, c0 + s1, p0, c0, p0, (int)K, 0, prec});
+      syrk_collect(c0 + s1, s2, p0, K, prec, all);
+      bool one_prec = true;
+      for (auto& nd : all) one_prec = one_prec && nd.prec == prec;
+      if (one_prec) {
+        bank = 1;
+        emit_group(all, prec, prec != F64, head);
+        bank = 0;
+        return true;
+      }
+      all.clear();
+    }
     syrk_collect(c0, s, p0, K, prec, all);
     for (int q = E4M3; q <= F64; q++) {
       std::vector<Node> sel;
@@ -523,6 +600,7 @@ struct Builder {
         if (nd.prec == q) sel.push_back(nd);
       emit_group(sel, q, q != F64);
     }
+    return false;
   }
 
   // ---- Tree-TRSM / Tree-SYRK on their own: the precision list is read by
@@ -612,8 +690,10 @@ struct Builder {
     }
   }
 
-  // ---- Algorithm 1
-  void potrf(int64_t i0, int64_t m, int depth) {
+  // ---- Algorithm 1.  join_tail: the Tree-SYRK that updated this block left
+  // its tail (everything but the leading block) on the side stream; the
+  // Tree-TRSM below the leading block waits for it.
+  void potrf(int64_t i0, int64_t m, int depth, bool join_tail = false) {
     if (m <= 0) return;
     if (m <= t.leaf) {
       leaf_potrf(i0, m);
@@ -627,9 +707,17 @@ struct Builder {
       P.split1 = m1;
       P.first_outer = (int)P.launches.size();
     }
+    const size_t first_trsm = P.launches.size();
     trsm(i0 + m1, m2, i0, m1, p);
-    syrk(i0 + m1, m2, i0, m1, p);
-    potrf(i0 + m1, m2, depth + 1);
+    if (join_tail) {
+      P.launches[first_trsm].wait_side = 1;
+      tail_pending = false;
+    }
+    const bool split = lookahead && !single_wg && !tail_pending && m2 > t.leaf &&
+                       (lookahead == 1 || p == F32 || p == F64);
+    const bool tail = syrk(i0 + m1, m2, i0, m1, p, split);
+    if (tail) tail_pending = true;
+    potrf(i0 + m1, m2, depth + 1, tail);
   }
 };
 
@@ -673,7 +761,8 @@ void build_syrk_plan(Plan& P, int64_t n, int64_t k, int64_t ldl, const mpchol_tr
   P.stats.n_launch = (int64_t)P.launches.size();
 }
 
-void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg, int tile) {
+void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg, int tile,
+                int lookahead) {
   P.n = n;
   P.ldl = ldl;
   P.tree = *t;
@@ -682,7 +771,9 @@ void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool sing
   Builder B(P, P.tree, ldl);
   B.single_wg = single_wg;
   B.tile_force = tile;
+  B.lookahead = single_wg ? 0 : lookahead;
   B.potrf(0, n, 0);
+  B.place_banks();
   P.stats.n_launch = (int64_t)P.launches.size();
 }
 

@@ -23,6 +23,10 @@ struct Launch {
   int64_t off = 0;                        // POTRF / TRINV / TRSM: element offset in the slot
                                           // (INVJOIN: a0 = i0, a1 = m, a2 = m1)
   int tile = 128;                         // GEMM output tile (32, 64, 128 or 256)
+  // Lookahead (single-matrix path): side = 1 runs the launch on the side
+  // stream once the caller's stream has reached it; wait_side = 1 makes the
+  // caller's stream wait for the side stream's work before this launch.
+  int side = 0, wait_side = 0;
 };
 
 struct PlanStats {
@@ -47,6 +51,7 @@ struct Plan {
   int ninv = 0;            // leaf-inverse slots (kInvLd x kInvLd doubles each)
   int64_t split1 = 0;      // order of the top-level A11 (0: the root is a leaf)
   int first_outer = -1;    // first launch that touches rows >= split1
+  int n_side = 0;          // launches on the side stream (lookahead tails)
   PlanStats stats;
   // device copies of the descriptor arrays
   MaxabsJob* d_maxabs = nullptr;
@@ -60,9 +65,23 @@ std::string plan_key(int64_t n, int64_t ldl, const mpchol_tree* t);
 // single_wg: the plan runs inside one workgroup (batched executor); GEMM
 // tiles are chosen for per-workgroup efficiency instead of chip occupancy.
 // tile: 0 automatic, 64 or 128 forces the GEMM output tile.
+// lookahead: split each Tree-SYRK of Algorithm 1 into the part that updates
+// A22's leading block (the block Tree-POTRF(A22) factors first) and the rest,
+// run the rest on a side stream while the leading block is factored, and join
+// before the Tree-TRSM of A22 (one tail in flight at a time; its operand
+// copies live in a second workspace bank).  lookahead 1: every Tree-SYRK;
+// 2: only FP32 / FP64 ones (FP16 / E4M3 GEMMs never share the GPU); 0: off.
+// Ignored with single_wg.
 void build_plan(Plan& P, int64_t n, int64_t ldl, const mpchol_tree* t, bool single_wg = false,
-                int tile = 0);
+                int tile = 0, int lookahead = 0);
 int64_t split_rule(int64_t m, int32_t align);
+// The block-scale mode the kernels apply to an operand of precision prec:
+// scale_mode 2 (E4M3 scaled both ways, the other formats only down) is
+// resolved here, per launch, into 1 for E4M3 and 0 otherwise, so that the
+// device-side block scale keeps its two modes.
+inline int operand_scale_mode(int scale_mode, int prec) {
+  return scale_mode == 2 ? (prec == MPCHOL_E4M3 ? 1 : 0) : scale_mode;
+}
 // Tree-TRSM (Algorithm 2) / Tree-SYRK (Algorithm 3) on their own, on blocks of
 // one matrix (ld ldl) as Algorithm 1 calls them: TRSM A21 = (k, 0, m x k)
 // against L11 = (0, 0, k x k); SYRK A22 = (k, k, n x n) -= A21 A21^T with

@@ -36,31 +36,34 @@ struct StatJob {
   int32_t part0, nparts, cpw, wg_start;
 };
 
-constexpr int kMlpIn = 5, kMlpH = 64, kMlpOut = 4;
-// flat float parameters: mu(5) sigma(5) W1(64x5) b1(64) W2(64x64) b2(64)
+constexpr int kMlpIn = 6, kMlpH = 64, kMlpOut = 4;
+// flat float parameters: mu(6) sigma(6) W1(64x6) b1(64) W2(64x64) b2(64)
 // W3(4x64) b3(4), matrices row-major (out x in)
-constexpr int kOffMu = 0, kOffSigma = 5, kOffW1 = 10, kOffB1 = kOffW1 + kMlpH * kMlpIn,
+constexpr int kOffMu = 0, kOffSigma = kMlpIn, kOffW1 = 2 * kMlpIn,
+              kOffB1 = kOffW1 + kMlpH * kMlpIn,
               kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
               kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpOut * kMlpH,
               kMlpParams = kOffB3 + kMlpOut;
 constexpr int kMlpTrained = kMlpParams - kOffW1;   // mu, sigma are set from the data
 constexpr int kMlpRows = 64;                        // rows per workgroup of the gradient kernel
 
+// rowpart / colsum: off-diagonal |a_ij| sums (use_max = 0) or maxima (1)
 hipError_t launch_rowabs(const double* A, int64_t lda, int64_t n, double* rowpart,
-                         double* colsum, hipStream_t s);
+                         double* colsum, int use_max, hipStream_t s);
 hipError_t launch_row_ratio(const double* A, int64_t lda, int64_t n, const double* rowpart,
-                            const double* colsum, double* ratio, hipStream_t s);
+                            const double* colsum, const double* rowmax, const double* colmax,
+                            double* ratio, double* gap, hipStream_t s);
 hipError_t launch_stats(const double* M, int64_t ld, const StatJob* jobs, int njobs, int total,
                         const double* scales, double* parts, hipStream_t s);
 hipError_t launch_node_features(const PNode* nodes, int n_nodes, const double* A, int64_t lda,
                                 const StatJob* jobs, const double* parts, const double* ratio,
-                                float* feat, hipStream_t s);
+                                const double* gap, float* feat, hipStream_t s);
 hipError_t launch_node_scales(int n_nodes, const StatJob* jobs, const double* parts,
                               int scale_mode, double* scales, hipStream_t s);
 hipError_t launch_node_labels(const PNode* nodes, int n_nodes, const StatJob* xjobs,
                               const double* xparts, const StatJob* ajobs, const double* aparts,
-                              double tau, const double* g, double sum_s2, double* err,
-                              int32_t* labels, hipStream_t s);
+                              double tau, const double* g, double sum_s2, int min_prec,
+                              double* err, int32_t* labels, hipStream_t s);
 hipError_t launch_pivot_ratio(const double* L, int64_t ldl, int64_t n, double* g, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t rows, const float* X, const float* params, float* probs,
                               int32_t* cls, hipStream_t s);

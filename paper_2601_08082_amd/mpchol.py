@@ -106,7 +106,7 @@ def _load() -> ct.CDLL:
     lib.mpchol_policy_nodes.restype = i64
     lib.mpchol_policy_features.argtypes = [vp, i64, vp, i64, ct.POINTER(CTree), vp, vp]
     lib.mpchol_policy_labels.argtypes = [vp, i64, vp, i64, vp, i64, ct.POINTER(CTree), dbl, i32,
-                                         vp, vp, vp]
+                                         i32, vp, vp, vp]
     lib.mpchol_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     lib.mpchol_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, ct.c_float, vp, vp,
                                           vp]
@@ -333,7 +333,7 @@ class Context:
 
     # ------------------------------------------------------------ learned policy
     def policy_features(self, A_cm, n: int, tree: Tree, stream=None):
-        """(nodes, 5) float32 device tensor of per-node features."""
+        """(nodes, MLP_IN) float32 device tensor of per-node features."""
         import torch
         _check_cm(A_cm, "A")
         nn = policy_nodes(n, tree).shape[0]
@@ -345,7 +345,7 @@ class Context:
         return feat[:nn]
 
     def policy_labels(self, A_cm, L_cm, n: int, tree: Tree, tau: float = 1e-4,
-                      scale_mode: int = 1, stream=None):
+                      scale_mode: int = 1, min_prec: int = E4M3, stream=None):
         """(labels int32 (nodes,), errors float64 (nodes, 3)) device tensors."""
         import torch
         nn = policy_nodes(n, tree).shape[0]
@@ -353,13 +353,13 @@ class Context:
         err = torch.empty((max(nn, 1), 3), dtype=torch.float64, device=A_cm.device)
         t, keep = tree.to_c()
         r = lib.mpchol_policy_labels(self._h, n, _ptr(A_cm), A_cm.shape[1], _ptr(L_cm),
-                                     L_cm.shape[1], ct.byref(t), tau, scale_mode,
+                                     L_cm.shape[1], ct.byref(t), tau, scale_mode, min_prec,
                                      err.data_ptr(), lab.data_ptr(), _stream_handle(stream))
         _raise(r, "mpchol_policy_labels")
         return lab[:nn], err[:nn]
 
     def mlp_forward(self, X, params, stream=None):
-        """(probs (rows, 4), classes (rows,)) for float32 features X (rows, 5)."""
+        """(probs (rows, 4), classes (rows,)) for float32 features X (rows, MLP_IN)."""
         import torch
         rows = X.shape[0]
         probs = torch.empty((max(rows, 1), MLP_OUT), dtype=torch.float32, device=X.device)
@@ -437,8 +437,8 @@ class Context:
         return r, [infos[i].as_dict() for i in range(batch)]
 
 
-MLP_IN, MLP_H, MLP_OUT = 5, 64, 4
-MLP_PARAMS = 4814
+MLP_IN, MLP_H, MLP_OUT = 6, 64, 4
+MLP_PARAMS = 4880
 
 
 NOALLOC_MAX_N = 16384
