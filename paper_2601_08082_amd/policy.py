@@ -205,6 +205,13 @@ def fp64_tree(leaf: int = 256, split_align: int = 1) -> "M.Tree":
     return M.Tree(leaf=leaf, offdiag=[M.F64], split_align=split_align)
 
 
+def three_level_tree(leaf: int = 256, split_align: int = 1) -> "M.Tree":
+    """The paper's three-level layering (Section 4.2): FP16 at the outermost
+    level, FP32 at the next, FP64 below, FP64 leaves."""
+    return M.Tree(leaf=leaf, offdiag=[M.F16, M.F32, M.F64], leaf_prec=M.F64,
+                  split_align=split_align)
+
+
 def learned_tree(tree, choice) -> "M.Tree":
     return M.Tree(leaf=tree.leaf, offdiag=list(tree.offdiag), leaf_prec=tree.leaf_prec,
                   split_align=tree.split_align, scale_mode=SCALE_MODE, node_prec=list(choice))
@@ -246,15 +253,18 @@ def measure(ctx, A, B, n: int, params, tree, tol: float = 1e-12, max_iter: int =
     """Measured time to a refined solution (correction below `tol`), inputs
     resident on the device, median of `reps` after one warm-up, for: the
     learned tree (choice of precisions included) with its fallback chain, the
-    fixed paper tree falling back to FP64, and the all-FP64 tree."""
+    fixed all-FP16 tree and the paper's three-level tree (each falling back
+    to FP64), and the all-FP64 tree."""
     import torch
     L = torch.empty_like(A)
     X = torch.empty_like(B)
     fx = [("fixed", fixed_tree(tree.leaf, tree.split_align)),
           ("fp64", fp64_tree(tree.leaf, tree.split_align))]
+    three = [("three_level", three_level_tree(tree.leaf, tree.split_align)), fx[1]]
     runs = {
         "learned": lambda: solve_with_policy(ctx, A, B, n, params, tree, tol, max_iter, L, X),
         "fixed": lambda: run_chain(ctx, A, B, n, fx, tol, max_iter, L, X),
+        "three_level": lambda: run_chain(ctx, A, B, n, three, tol, max_iter, L, X),
         "fp64": lambda: run_chain(ctx, A, B, n, fx[1:], tol, max_iter, L, X),
     }
     out = {}
@@ -277,6 +287,7 @@ def measure(ctx, A, B, n: int, params, tree, tol: float = 1e-12, max_iter: int =
             rec["node_prec"] = ch
         out[name] = rec
     out["gain_vs_fixed"] = out["fixed"]["tts_ms"] / out["learned"]["tts_ms"]
+    out["gain_vs_three_level"] = out["three_level"]["tts_ms"] / out["learned"]["tts_ms"]
     out["gain_vs_fp64"] = out["fp64"]["tts_ms"] / out["learned"]["tts_ms"]
     return out
 
