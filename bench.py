@@ -368,6 +368,11 @@ def main() -> int:
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    # release the device memory while the process is still fully up (a
+    # profiler attached to the run writes its output at exit)
+    del A, B, L, X
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     ctx.close()
     return 0
 

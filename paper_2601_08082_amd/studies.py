@@ -2,6 +2,7 @@
 
     python -m paper_2601_08082_amd.studies subkernels [--sizes 8192,16384,...]
     python -m paper_2601_08082_amd.studies depth [--sizes ...] [--max-depth 6]
+    python -m paper_2601_08082_amd.studies step [--sizes 65536] [--steps 3]
 
 subkernels: Tree-SYRK and Tree-TRSM on their own (mpchol_syrk / mpchol_trsm),
 at the shapes the outermost Tree-POTRF level issues for an order-n matrix
@@ -11,6 +12,10 @@ schedule run entirely in its diagonal (last) precision.
 depth: the whole factorization (mpchol_factor) for precision lists of
 increasing depth, [F16] * d + [F32] and [F16] * d + [F64], leaf 256, against
 the all-F32 / all-F64 tree of the same schedule: time, speedup, backward error.
+step: the benchmark's step on its own (factor with [F16,F32,F64] over a leaf
+of 256 in FP64, then the FP64-refined solve of 16 right-hand sides, dominance
+ratio 1.2), a few times, with nothing else in the process: the command a
+kernel-trace profiler wraps.
 
 Inputs are the synthetic diagonally dominant SPD matrices of the benchmark
 (dominance ratio 1.5) generated on the device; times are the medians of five
@@ -22,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import sys
+import time
 
 import numpy as np
 
@@ -110,15 +116,44 @@ def depth(sizes, max_depth):
     ctx.close()
 
 
+def step(sizes, steps):
+    import torch
+    from paper_2601_08082_amd import mpchol as M
+    from paper_2601_08082_amd import spdgen_gpu
+    ctx = M.Context(0)
+    tree = M.Tree(leaf=256, offdiag=[M.F16, M.F32, M.F64], leaf_prec=M.F64)
+    for n in sizes:
+        A = spdgen_gpu.gen_spd(n, 1.2, 0.0, seed=8, lda=n)
+        B = spdgen_gpu.gen_rhs(n, 16, seed=108, ldb=n)
+        L = torch.empty_like(A)
+        X = torch.empty_like(B)
+        for i in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.factor(A, n, tree, L_cm=L, sync=False)
+            _, s = ctx.solve(L, B, n, A_cm=A, tol=1e-13, max_iter=20, X_cm=X)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            print(json.dumps({"study": "step", "n": n, "step": i, "ms": ms,
+                              "ir_iters": s["ir_iters"], "status": s["status"]}), flush=True)
+        del A, B, L, X
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    ctx.close()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["subkernels", "depth"])
+    ap.add_argument("study", choices=["subkernels", "depth", "step"])
     ap.add_argument("--sizes", default="8192,16384,32768,65536")
     ap.add_argument("--max-depth", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=3)
     a = ap.parse_args()
     sizes = [int(x) for x in a.sizes.split(",")]
     if a.study == "subkernels":
         subkernels(sizes)
+    elif a.study == "step":
+        step(sizes, a.steps)
     else:
         depth(sizes, a.max_depth)
     return 0
