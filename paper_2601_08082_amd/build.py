@@ -14,14 +14,17 @@ LIB = os.path.join(HERE, "libmpchol.so")
 GENLIB = os.path.join(HERE, "libspdgen.so")
 ARCH = os.environ.get("MPCHOL_ARCH", "gfx950")
 
-SOURCES = ["k_quant.hip", "k_gemm.hip", "k_leaf.hip", "k_trsm_inv.hip", "k_solve.hip",
+SOURCES = ["k_quant.hip", "k_gemm.hip", "k_gemm_f32f64.hip", "k_leaf.hip", "k_trsm_inv.hip", "k_solve.hip",
            "k_batched.hip", "k_policy.hip", "k_check.hip", "plan.cpp", "capi.cpp"]
 # the leaf kernels round every a*b and every subtraction separately, in the
 # order of the textbook elimination; their elimination chains are latency
 # bound, and the ILP-oriented scheduler starts each column's square root before
 # the updates that the next column does not need
 EXTRA = {"k_leaf.hip": ["-ffp-contract=off", "-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-         "k_trsm_inv.hip": ["-ffp-contract=off"], "k_batched.hip": ["-ffp-contract=off"]}
+         "k_trsm_inv.hip": ["-ffp-contract=off"], "k_batched.hip": ["-ffp-contract=off"],
+         # FP32 / FP64 GEMMs: VGPR-form MFMAs keep the 128-tile kernels at two
+         # waves per SIMD with the accumulators in place
+         "k_gemm_f32f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 GEN_SOURCES = ["spdgen.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -5,6 +5,8 @@
 #include "internal.h"
 #include "numfmt.h"
 
+#include <type_traits>
+
 namespace mpc {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -557,34 +559,29 @@ __device__ inline void gemm_f32q_tile(double* __restrict__ Lm, int64_t ldl,
   const int wm = wave & 1, wn = wave >> 1;
 
   // unconditional loads (K clamped into the copy), padding masked at the LDS
-  // store; two register sets in flight, double-buffered LDS
-  uint4 rx[2][NV], ry[2][NV];
-  auto gload = [&](int k0, uint4 (&vx)[NV], uint4 (&vy)[NV]) {
-    if (!direct) {
+  // store; double-buffered LDS.  The common case (operands from the copies)
+  // keeps two register sets of loads in flight; the rare direct case (an
+  // operand converted from the factor on the way in) keeps one, so that its
+  // conversions do not set the kernel's register count.
+  auto gload = [&](int k0, uint4* vx, uint4* vy, auto dir) {
 #pragma unroll
-      for (int i = 0; i < NV; i++) {
-        int v = tid + 256 * i;
-        int row = v / CPR, ch = v % CPR;
-        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
-        const int kc = min(k0 + ch * 4, kv - 4);
-        vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
-        vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; i++) {
-        int v = tid + 256 * i;
-        int row = v / CPR, ch = v % CPR;
-        int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
-        const int kc = min(k0 + ch * 4, kv - 4);
+    for (int i = 0; i < NV; i++) {
+      int v = tid + 256 * i;
+      int row = v / CPR, ch = v % CPR;
+      int gx = min(m0 + row, P.m - 1), gy = min(n0 + row, P.n - 1);
+      const int kc = min(k0 + ch * 4, kv - 4);
+      if constexpr (decltype(dir)::value) {
         vx[i] = xdir ? direct_chunk<float>(Lm, ldl, P.xsrc, gx, kc, P.k, isx, prec)
                      : *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
         vy[i] = ydir ? direct_chunk<float>(Lm, ldl, P.ysrc, gy, kc, P.k, isy, prec)
                      : *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
+      } else {
+        vx[i] = *reinterpret_cast<const uint4*>(X + (int64_t)gx * P.ldx + kc);
+        vy[i] = *reinterpret_cast<const uint4*>(Y + (int64_t)gy * P.ldy + kc);
       }
     }
   };
-  auto sstore = [&](int buf, int k0, const uint4 (&vx)[NV], const uint4 (&vy)[NV]) {
+  auto sstore = [&](int buf, int k0, const uint4* vx, const uint4* vy) {
 #pragma unroll
     for (int i = 0; i < NV; i++) {
       int v = tid + 256 * i;
@@ -626,27 +623,46 @@ __device__ inline void gemm_f32q_tile(double* __restrict__ Lm, int64_t ldl,
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][j], bf[b][j], acc[a][b], 0, 0, 0);
     }
   };
-  auto step = [&](int kt, uint4 (&nx)[NV], uint4 (&ny)[NV], uint4 (&sx)[NV], uint4 (&sy)[NV]) {
-    gload((kt + 2) * BK, nx, ny);
-    // keep the loads ahead of the products (the scheduler would otherwise
-    // sink them to their use and wait for them on the spot)
-    __builtin_amdgcn_sched_barrier(0);
-    compute(kt & 1);
-    // unconditional (past the end it fills a buffer nobody reads)
-    sstore((kt + 1) & 1, (kt + 1) * BK, sx, sy);
-    __syncthreads();
-  };
 
-  gload(0, rx[0], ry[0]);
-  gload(BK, rx[1], ry[1]);
-  sstore(0, 0, rx[0], ry[0]);
-  __syncthreads();
-  int kt = 0;
-  for (; kt + 1 < nk; kt += 2) {
-    step(kt, rx[0], ry[0], rx[1], ry[1]);
-    step(kt + 1, rx[1], ry[1], rx[0], ry[0]);
+  if (!direct) {
+    constexpr std::false_type dir{};
+    uint4 rx[2][NV], ry[2][NV];
+    // step kt: loads of step kt + 2 into the set freed at step kt - 1,
+    // multiply LDS buffer kt & 1, then store the other set's step kt + 1
+    auto step = [&](int kt, uint4 (&nx)[NV], uint4 (&ny)[NV], uint4 (&sx)[NV], uint4 (&sy)[NV]) {
+      gload((kt + 2) * BK, nx, ny, dir);
+      // keep the loads ahead of the products (the scheduler would otherwise
+      // sink them to their use and wait for them on the spot)
+      __builtin_amdgcn_sched_barrier(0);
+      compute(kt & 1);
+      // unconditional (past the end it fills a buffer nobody reads)
+      sstore((kt + 1) & 1, (kt + 1) * BK, sx, sy);
+      __syncthreads();
+    };
+    gload(0, rx[0], ry[0], dir);
+    gload(BK, rx[1], ry[1], dir);
+    sstore(0, 0, rx[0], ry[0]);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+      step(kt, rx[0], ry[0], rx[1], ry[1]);
+      step(kt + 1, rx[1], ry[1], rx[0], ry[0]);
+    }
+    if (kt < nk) step(kt, rx[0], ry[0], rx[1], ry[1]);
+  } else {
+    constexpr std::true_type dir{};
+    uint4 rx[NV], ry[NV];
+    gload(0, rx, ry, dir);
+    sstore(0, 0, rx, ry);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt++) {
+      gload((kt + 1) * BK, rx, ry, dir);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(kt & 1);
+      sstore((kt + 1) & 1, (kt + 1) * BK, rx, ry);
+      __syncthreads();
+    }
   }
-  if (kt < nk) step(kt, rx[0], ry[0], rx[1], ry[1]);
 
   // C tile, one 16-column strip of the wave tile at a time: every load of
   // the strip first (addresses clamped into the block), then the stores

@@ -91,6 +91,14 @@ hipError_t launch_cast_max(const double* Lm, int64_t ldl, const CastJob* jobs, i
 hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* ws,
                        const GemmProb* probs, int nprobs, int total_tiles, const double* part,
                        int scale_mode, DevStatus* st, hipStream_t s);
+// FP32 problems of launch_gemm (tiles 32, 64, 128) and FP64 problems with
+// 64 or 128 tiles (grid g, one tile per workgroup; FP64 requires
+// ldl < 2^23).
+hipError_t launch_gemm_f32q(int tile, dim3 g, double* Lm, int64_t ldl, const float* ws,
+                            const GemmProb* probs, int nprobs, const double* part, int prec,
+                            int scale_mode, DevStatus* st, hipStream_t s);
+hipError_t launch_gemm_d64(int tile, dim3 g, double* Lm, int64_t ldl, const GemmProb* probs,
+                           int nprobs, hipStream_t s);
 hipError_t launch_potrf_leaf(int prec, double* Lm, int64_t ldl, int64_t i0, int m,
                              DevStatus* st, hipStream_t s);
 // FP64 leaf inverses: of a kernel leaf (m <= KL) into a KL x KL block of Y

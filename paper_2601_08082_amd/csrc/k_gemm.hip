@@ -38,18 +38,6 @@ __global__ __launch_bounds__(kQ256Threads) void k_gemm_q256(double* __restrict__
   gemm_q256_tile<_Float16>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
 }
 
-template <int BM>
-__global__ __launch_bounds__(256) void k_gemm_f32q(double* __restrict__ Lm, int64_t ldl,
-                                                   const float* __restrict__ ws,
-                                                   const GemmProb* __restrict__ probs, int nprobs,
-                                                   const double* __restrict__ part, int prec,
-                                                   int scale_mode, DevStatus* st) {
-  __shared__ __attribute__((aligned(16))) char pool[gemm_f32q_lds_bytes<BM>()];
-  const int w = xcd_tile(blockIdx.x, gridDim.x);
-  const GemmProb P = probs[find_prob(probs, nprobs, w)];
-  gemm_f32q_tile<BM>(Lm, ldl, ws, P, w - P.tile_start, part, prec, scale_mode, st, pool);
-}
-
 template <typename T, int BM>
 __global__ __launch_bounds__(256) void k_gemm_d(double* __restrict__ Lm, int64_t ldl,
                                                 const GemmProb* __restrict__ probs, int nprobs,
@@ -75,12 +63,15 @@ static void launch_gemm_bm(int prec, dim3 g, dim3 b, hipStream_t s, double* Lm, 
                          (const unsigned char*)ws, probs, nprobs, part, prec, scale_mode, st);
       break;
     case F32:   // FP32 workspace copies
-      hipLaunchKernelGGL((k_gemm_f32q<BM>), g, b, 0, s, Lm, ldl, (const float*)ws, probs, nprobs,
-                         part, prec, scale_mode, st);
+      launch_gemm_f32q(BM, g, Lm, ldl, (const float*)ws, probs, nprobs, part, prec, scale_mode, st,
+                       s);
       break;
     default:
-      hipLaunchKernelGGL((k_gemm_d<double, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
-                         scale_mode, st);
+      if (ldl < ((int64_t)1 << 23))   // every buffer offset of a K step fits 31 bits
+        launch_gemm_d64(BM, g, Lm, ldl, probs, nprobs, s);
+      else
+        hipLaunchKernelGGL((k_gemm_d<double, BM>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
+                           scale_mode, st);
       break;
   }
 }
@@ -98,8 +89,7 @@ hipError_t launch_gemm(int prec, int tile, double* Lm, int64_t ldl, const void* 
   } else if (tile == 128) {
     launch_gemm_bm<128>(prec, g, b, s, Lm, ldl, ws, probs, nprobs, part, scale_mode, st);
   } else if (tile == 32 && prec == F32) {   // small FP32 / FP64 groups: more workgroups
-    hipLaunchKernelGGL((k_gemm_f32q<32>), g, b, 0, s, Lm, ldl, (const float*)ws, probs, nprobs,
-                       part, prec, scale_mode, st);
+    launch_gemm_f32q(32, g, Lm, ldl, (const float*)ws, probs, nprobs, part, prec, scale_mode, st, s);
   } else if (tile == 32 && prec == F64) {
     hipLaunchKernelGGL((k_gemm_d<double, 32>), g, b, 0, s, Lm, ldl, probs, nprobs, part, prec,
                        scale_mode, st);
