@@ -187,34 +187,36 @@ constexpr unsigned long long kSentinel = 0x7FF4D5A1B2C3E4F5ull;
 
 // Values of a published block that still hold the sentinel are polled again
 // (all of a thread's pending values in flight at once) until they are final.
-__device__ inline void settle_poll(double (&xv)[4], const double* XP, const int64_t (&at)[4],
-                                   const bool (&use)[4], DevStatus* st) {
+template <int N>
+__device__ inline void settle_poll(double (&xv)[N], const double* XP, const int64_t (&at)[N],
+                                   const bool (&use)[N], DevStatus* st) {
   long spins = 0;
   for (;;) {
     __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-    for (int q = 0; q < 4; q++)
+    for (int q = 0; q < N; q++)
       if (use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel)
         xv[q] = coherent_load(XP + at[q]);
     bool pending = false;
 #pragma unroll
-    for (int q = 0; q < 4; q++)
+    for (int q = 0; q < N; q++)
       pending |= use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel;
     if (!pending) return;
     if (++spins > kSpinLimit) {
       atomicOr(&st->wait_timeout, 1u);
 #pragma unroll
-      for (int q = 0; q < 4; q++) xv[q] = 0.0;
+      for (int q = 0; q < N; q++) xv[q] = 0.0;
       return;
     }
   }
 }
 
-__device__ inline void settle(double (&xv)[4], const double* XP, const int64_t (&at)[4],
-                              const bool (&use)[4], DevStatus* st) {
+template <int N>
+__device__ inline void settle(double (&xv)[N], const double* XP, const int64_t (&at)[N],
+                              const bool (&use)[N], DevStatus* st) {
   bool pending = false;
 #pragma unroll
-  for (int q = 0; q < 4; q++)
+  for (int q = 0; q < N; q++)
     pending |= use[q] && (unsigned long long)__double_as_longlong(xv[q]) == kSentinel;
   if (pending) settle_poll(xv, XP, at, use, st);
 }
@@ -319,21 +321,30 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
       const int64_t k0 = (int64_t)blk_of(k) * NB;
       const int nk = nk_of(k);
       double* dst = ys + slot * NB * XSW;
+      // the first column of the lane's row is polled until it is final (one
+      // value per lane in flight while the block is not yet published, so
+      // the polls of every workgroup take little bandwidth from the tile
+      // streams), then the other 15 columns in one round trip
+      double yv[16];
+      int64_t at[16];
+      bool use[16];
 #pragma unroll
-      for (int c0 = 0; c0 < 16; c0 += 4) {
-        double yv[4];
-        int64_t at[4];
-        bool use[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          use[q] = l < nk && c0 + q < nrhs;
-          at[q] = (k0 + min(l, nk - 1)) + (int64_t)min(c0 + q, nrhs - 1) * n;
-          yv[q] = coherent_load(XP + at[q]);
-        }
-        settle(yv, XP, at, use, st);
-#pragma unroll
-        for (int q = 0; q < 4; q++) dst[l * XSW + c0 + q] = use[q] ? yv[q] : 0.0;
+      for (int q = 0; q < 16; q++) {
+        use[q] = l < nk && q < nrhs;
+        at[q] = (k0 + min(l, nk - 1)) + (int64_t)min(q, nrhs - 1) * n;
       }
+      {
+        double y0[1] = {coherent_load(XP + at[0])};
+        const int64_t a0[1] = {at[0]};
+        const bool u0[1] = {use[0]};
+        settle(y0, XP, a0, u0, st);
+        yv[0] = y0[0];
+      }
+#pragma unroll
+      for (int q = 1; q < 16; q++) yv[q] = coherent_load(XP + at[q]);
+      settle(yv, XP, at, use, st);
+#pragma unroll
+      for (int q = 0; q < 16; q++) dst[l * XSW + q] = use[q] ? yv[q] : 0.0;
       if (l == 0) lds_flag_store(&ready[slot], k + 1);
     }
     return;
