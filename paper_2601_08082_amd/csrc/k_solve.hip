@@ -43,16 +43,18 @@ __device__ inline double keep_or_zero(double v, bool keep) {
 // A 64 x 64 tile times a 64 x 16 block takes 16 MFMAs per wave; the tile's
 // elements go from global memory straight into the src0 registers (each lane
 // 16 of them), the 64 x 16 block is staged in LDS.  The k a lane supplies in
-// MFMA t is chosen for coalescing:
-//   forward (the tile's rows are the output rows): k = 4 t + g (g = l / 16),
-//     so one load instruction reads 16 consecutive rows of 4 columns;
-//   transposed (the tile's columns are the output rows): k = 16 g + t, so
-//     each lane walks 16 consecutive rows of one column.
+// MFMA t is k = 4 t + g (g = l / 16):
+//   forward (the tile's rows are the output rows): one load instruction
+//     reads 16 consecutive rows of 4 columns;
+//   transposed (the tile's columns are the output rows): one load
+//     instruction reads 4 consecutive rows of 16 columns, so it touches 16
+//     cache lines (k = 16 g + t, each lane walking its column, touched 64:
+//     measured slower for the residual's and the backward solve's reads).
 constexpr int XSW = 17;   // padded LDS row of a staged 64 x 16 block (doubles)
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline int kmap(bool trans, int t, int g) { return trans ? 16 * g + t : 4 * t + g; }
+__device__ inline int kmap(int t, int g) { return 4 * t + g; }
 
 // The 16 tile elements of this lane: element (o, k) of the tile with o the
 // lane's output row, at T[o * so + k * sk] (forward: so = 1, sk = ld;
@@ -80,8 +82,8 @@ __device__ inline void tile_load(const double* __restrict__ T, uint32_t so, uint
     // a uniform step (forward: 4 columns; transposed: one row, an immediate)
     // buffer loads: the tile's first element is the (uniform) base, the lane
     // offset one VGPR, the step of load t a scalar offset
-    const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(trans ? 16 * g : g) * bsk;
-    const uint32_t st = trans ? bsk : 4u * bsk;
+    const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)g * bsk;
+    const uint32_t st = 4u * bsk;
     const __amdgpu_buffer_rsrc_t rs = tile_rsrc(T);
 #pragma unroll
     for (int t = 0; t < 16; t++)
@@ -92,7 +94,7 @@ __device__ inline void tile_load(const double* __restrict__ T, uint32_t so, uint
   const uint32_t o = (uint32_t)min(16 * w + (l & 15), no - 1);
 #pragma unroll
   for (int t = 0; t < 16; t++) {
-    const uint32_t k = (uint32_t)min(kmap(trans, t, g), nk - 1);
+    const uint32_t k = (uint32_t)min(kmap(t, g), nk - 1);
     const uint32_t r = mirror ? max(o, k) : o, c = mirror ? min(o, k) : k;
     v[t] = *reinterpret_cast<const double*>(Tb + (r * bso + c * bsk));
   }
@@ -107,8 +109,8 @@ __device__ inline void tile_load_b(const double* __restrict__ T, uint32_t so, ui
                                    bool trans, uint32_t limit, double (&v)[16]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
   const uint32_t bso = so * 8u, bsk = sk * 8u;
-  const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(trans ? 16 * g : g) * bsk;
-  const uint32_t st = trans ? bsk : 4u * bsk;
+  const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)g * bsk;
+  const uint32_t st = 4u * bsk;
   const uint64_t a = reinterpret_cast<uint64_t>(T);
   const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)a);
   const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
@@ -129,7 +131,7 @@ __device__ inline void tile_mfma(const double (&v)[16], const double* xs, bool t
   const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
 #pragma unroll
   for (int t = 0; t < 16; t++) {
-    const int k = kmap(trans, t, g);
+    const int k = kmap(t, g);
     const double a = keep_or_zero(v[t], k < nk);
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xs[k * XSW + c], acc, 0, 0, 0);
   }
