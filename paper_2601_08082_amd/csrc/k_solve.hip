@@ -176,7 +176,12 @@ __device__ inline void xblock_coords(int nrows, int nrhs, int (&cidx)[4], int& i
 // Workgroup layout: four compute waves and one poller wave.  The poller
 // fetches each solved block the workgroup needs from the published copy
 // (polling until it is final) into a ring of kYRing LDS slots and raises the
-// slot's flag; the compute waves read it straight from the slot.  Vector loads
+// slot's flag; the compute waves read it straight from the slot.  A block the
+// workgroup solves itself goes the other way: the compute waves leave x_s in
+// an LDS staging buffer, and the poller copies it into its ring slot and
+// publishes it (the published copy first: those stores are the hop to the
+// next block's owner; the solution after).  A compute wave's stores would
+// queue behind its tile loads in flight; the poller has none.  Vector loads
 // retire in order per wave, so a wave that polls drains its own loads in
 // flight: keeping the polls in their own wave leaves the compute waves' tile
 // prefetches untouched.  The compute waves load each task's 64 x 64 block
@@ -254,7 +259,7 @@ constexpr int kTrsvThreads = 320;
 
 // LDS: the y ring, two buffers for the z products, one running sum per owned
 // block ([j][r][thread]), and the ring / progress / barrier words
-constexpr int kTrsvStaticLds = (kYRing * NB * XSW + 2 * NB * XSW) * 8 + 64 * 4;
+constexpr int kTrsvStaticLds = (kYRing * NB * XSW + 3 * NB * XSW) * 8 + 64 * 4;
 inline size_t trsv_lds_bytes(int rows) { return (size_t)kTrsvStaticLds + (size_t)rows * 4 * 256 * 8; }
 
 __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const double* __restrict__ Lm,
@@ -266,10 +271,12 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
   extern __shared__ __attribute__((aligned(16))) double trsv_pool[];
   double* ys = trsv_pool;                         // kYRing slots of 64 x XSW
   double* vs = ys + kYRing * NB * XSW;            // two buffers for the z products
-  int* words = reinterpret_cast<int*>(vs + 2 * NB * XSW);
+  double* stg = vs + 2 * NB * XSW;                // this workgroup's newest chain result
+  int* words = reinterpret_cast<int*>(stg + NB * XSW);
   int* ready = words;                             // [kYRing]: step + 1 of the slot's contents
   int* progress = words + 8;                      // [4]: step each compute wave has opened
   int* bar = words + 16;                          // z-product barrier arrivals
+  int* xcnt = words + 24;                         // compute waves' chain results staged
   double* accs = reinterpret_cast<double*>(words + 64);
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int nblk = (int)((n + NB - 1) / NB);
@@ -284,6 +291,7 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
   if (tid < kYRing) ready[tid] = 0;
   if (tid < 4) progress[tid] = -1;
   if (tid == 0) *bar = 0;
+  if (tid == 0) *xcnt = 0;
   if (tid < 256)
     for (int j = 0; j < nown; j++) {
       // running sums start at b
@@ -300,9 +308,16 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
   __syncthreads();   // the only workgroup-wide barrier
 
   if (w == 4) {
-    // poller: steps 0 .. (last owned block) - 1 in order
+    // poller: steps 0 .. (last owned block) in order.  A block this workgroup
+    // owns comes from its own chain step through the staging buffer, and the
+    // poller publishes it: its stores then wait behind no tile loads (the
+    // compute waves keep up to 64 in flight, and a store needs a free slot
+    // of the same per-wave count).  Any other block is polled from the
+    // published copy.
     const int last = row_of(nown - 1);
-    for (int k = 0; k < last; k++) {
+    int nch = 0;   // own chain results taken
+    for (int k = 0; k <= last; k++) {
+      const bool own = k >= o && (k - o) % P == 0;
       const int slot = k % kYRing;
       // the slot's previous step (k - kYRing) must be done by every compute wave
       long spins = 0;
@@ -323,6 +338,36 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
       const int64_t k0 = (int64_t)blk_of(k) * NB;
       const int nk = nk_of(k);
       double* dst = ys + slot * NB * XSW;
+      if (own) {
+        nch++;
+        long sp = 0;
+        while (lds_load_relaxed(xcnt) < 4 * nch) {
+          __builtin_amdgcn_s_sleep(0);
+          if (++sp > kSpinLimit) {
+            atomicOr(&st->wait_timeout, 1u);
+            return;
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // the published copy first (coherent across the dies without a
+        // fence; these stores are the hop), the solution after it
+        double xr[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+          xr[q] = stg[l * XSW + q];
+          if (l < nk && q < nrhs)
+            __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (k0 + l) + (int64_t)q * n),
+                               (unsigned long long)__double_as_longlong(xr[q]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) dst[l * XSW + q] = (l < nk && q < nrhs) ? xr[q] : 0.0;
+        if (l == 0) lds_flag_store(&ready[slot], k + 1);
+#pragma unroll
+        for (int q = 0; q < 16; q++)
+          if (l < nk && q < nrhs) X[(k0 + l) + (int64_t)q * ldx] = xr[q];
+        continue;
+      }
       // the first column of the lane's row is polled until it is final (one
       // value per lane in flight while the block is not yet published, so
       // the polls of every workgroup take little bandwidth from the tile
@@ -494,23 +539,14 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
       for (int r = 0; r < 4; r++) acc_j[r * 256] = z[r];
       return true;
     }
-    // chain step: x_s = z_s - M_s x_{s-1} (x_0 = z_0); publish
+    // chain step: x_s = z_s - M_s x_{s-1} (x_0 = z_0), into the staging
+    // buffer; the poller wave publishes it
     f64x4_t mx = {0.0, 0.0, 0.0, 0.0};
     if (sb > 0) tile_mfma(v, yk, false, NB, mx);
-    const int64_t j0 = (int64_t)blk_of(sb) * NB;
-    const int nj = nk_of(sb);
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int row = orow + 4 * r;
-      if (row < nj && ocol < nrhs) {
-        const double x = acc_j[r * 256] - mx[r];
-        X[(j0 + row) + (int64_t)ocol * ldx] = x;
-        // the published copy, coherent across the dies without a fence
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(XP + (j0 + row) + (int64_t)ocol * n),
-                           (unsigned long long)__double_as_longlong(x), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    for (int r = 0; r < 4; r++) stg[(orow + 4 * r) * XSW + ocol] = acc_j[r * 256] - mx[r];
+    lds_settle();
+    if (l == 0) lds_flag_add(xcnt, 1);
     return true;
   };
 
@@ -526,27 +562,21 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
   advance(ti);
   issue(ti, S3);
   advance(ti);
+  // one ring stage: issue task ti into the slot si freed the stage before,
+  // then execute task te from slot se
+  auto stage = [&](double (&se)[16], double (&si)[16]) -> bool {
+    issue(ti, si);
+    advance(ti);
+    if (!exec(te, se)) return false;
+    advance(te);
+    return true;
+  };
   for (;;) {
-    issue(ti, S4);
-    advance(ti);
-    if (!exec(te, S0)) break;
-    advance(te);
-    issue(ti, S0);
-    advance(ti);
-    if (!exec(te, S1)) break;
-    advance(te);
-    issue(ti, S1);
-    advance(ti);
-    if (!exec(te, S2)) break;
-    advance(te);
-    issue(ti, S2);
-    advance(ti);
-    if (!exec(te, S3)) break;
-    advance(te);
-    issue(ti, S3);
-    advance(ti);
-    if (!exec(te, S4)) break;
-    advance(te);
+    if (!stage(S0, S4)) break;
+    if (!stage(S1, S0)) break;
+    if (!stage(S2, S1)) break;
+    if (!stage(S3, S2)) break;
+    if (!stage(S4, S3)) break;
   }
   // no step is opened any more: release the poller's ring
   lds_settle();
