@@ -43,18 +43,22 @@ __device__ inline double keep_or_zero(double v, bool keep) {
 // A 64 x 64 tile times a 64 x 16 block takes 16 MFMAs per wave; the tile's
 // elements go from global memory straight into the src0 registers (each lane
 // 16 of them), the 64 x 16 block is staged in LDS.  The k a lane supplies in
-// MFMA t is k = 4 t + g (g = l / 16):
+// MFMA t is k = 8 (t / 2) + 2 g + t % 2 (g = l / 16), so MFMAs 2m and 2m + 1
+// take two adjacent k:
 //   forward (the tile's rows are the output rows): one load instruction
 //     reads 16 consecutive rows of 4 columns;
-//   transposed (the tile's columns are the output rows): one load
-//     instruction reads 4 consecutive rows of 16 columns, so it touches 16
-//     cache lines (k = 16 g + t, each lane walking its column, touched 64:
-//     measured slower for the residual's and the backward solve's reads).
+//   transposed (the tile's columns are the output rows): a lane's two
+//     adjacent k are adjacent in memory, so one 16-byte load instruction
+//     reads 8 rows of 16 columns (16 cache lines, 8 instructions a tile),
+//     or two 8-byte ones when the stride is odd.  (One lane per column
+//     walking 16 rows touched 64 lines per instruction and was slower.)
 constexpr int XSW = 17;   // padded LDS row of a staged 64 x 16 block (doubles)
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline int kmap(int t, int g) { return 4 * t + g; }
+__device__ inline int kmap(int t, int g) { return 8 * (t >> 1) + 2 * g + (t & 1); }
+// byte offset of load t from the lane's first element, k stride bsk
+__device__ inline uint32_t kstep(int t, uint32_t bsk) { return (uint32_t)(8 * (t >> 1) + (t & 1)) * bsk; }
 
 // The 16 tile elements of this lane: element (o, k) of the tile with o the
 // lane's output row, at T[o * so + k * sk] (forward: so = 1, sk = ld;
@@ -72,23 +76,36 @@ __device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const double* p) {
                                            0x7fffffff, 0x00020000);
 }
 
+// PAIRS (transposed reads only): the lane's two adjacent k come in one
+// 16-byte load; the caller guarantees 16-byte alignment (T at an even
+// element, an even stride so).
+template <bool PAIRS = false>
 __device__ inline void tile_load(const double* __restrict__ T, uint32_t so, uint32_t sk, bool trans,
                                  bool mirror, int no, int nk, double (&v)[16]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
   const char* __restrict__ Tb = reinterpret_cast<const char*>(T);
   const uint32_t bso = so * 8u, bsk = sk * 8u;   // byte strides
   if (!mirror && no == NB && nk == NB) {
-    // a whole tile (uniform): one lane offset for all 16 loads, the load index
-    // a uniform step (forward: 4 columns; transposed: one row, an immediate)
-    // buffer loads: the tile's first element is the (uniform) base, the lane
-    // offset one VGPR, the step of load t a scalar offset
-    const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)g * bsk;
-    const uint32_t st = 4u * bsk;
+    // a whole tile (uniform): one lane offset for all loads, the load index a
+    // uniform step.  Buffer loads: the tile's first element is the (uniform)
+    // base, the lane offset one VGPR, the step of load t a scalar offset
+    const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(2 * g) * bsk;
     const __amdgpu_buffer_rsrc_t rs = tile_rsrc(T);
+    if (PAIRS && trans) {
+#pragma unroll
+      for (int m = 0; m < 8; m++) {
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(
+            rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(64 * m), 0);
+        v[2 * m] = __longlong_as_double((long long)(((unsigned long long)q.y << 32) | q.x));
+        v[2 * m + 1] = __longlong_as_double((long long)(((unsigned long long)q.w << 32) | q.z));
+      }
+      return;
+    }
 #pragma unroll
     for (int t = 0; t < 16; t++)
       v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                            rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(t * st), 0));
+                                            rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(kstep(t, bsk)), 0));
     return;
   }
   const uint32_t o = (uint32_t)min(16 * w + (l & 15), no - 1);
@@ -109,8 +126,7 @@ __device__ inline void tile_load_b(const double* __restrict__ T, uint32_t so, ui
                                    bool trans, uint32_t limit, double (&v)[16]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4;
   const uint32_t bso = so * 8u, bsk = sk * 8u;
-  const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)g * bsk;
-  const uint32_t st = 4u * bsk;
+  const uint32_t lo = (uint32_t)(16 * w + (l & 15)) * bso + (uint32_t)(2 * g) * bsk;
   const uint64_t a = reinterpret_cast<uint64_t>(T);
   const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)a);
   const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
@@ -120,7 +136,7 @@ __device__ inline void tile_load_b(const double* __restrict__ T, uint32_t so, ui
 #pragma unroll
   for (int t = 0; t < 16; t++)
     v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                          rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(t * st), 0));
+                                          rs, (int)lo, (int)__builtin_amdgcn_readfirstlane(kstep(t, bsk)), 0));
 }
 
 // acc += tile (no x nk valid) times the staged block xs (k x 16, row stride
@@ -826,6 +842,8 @@ __device__ inline void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// PAIRS: the transposed reads in 16-byte loads (A 16-byte aligned, lda even).
+template <bool PAIRS>
 __global__ __launch_bounds__(256, 1) void k_resid4(const double* __restrict__ A, int64_t lda,
                                                    int64_t n, int nrhs,
                                                    const double* __restrict__ X, int64_t ldx,
@@ -887,7 +905,7 @@ __global__ __launch_bounds__(256, 1) void k_resid4(const double* __restrict__ A,
     const double* T = A + (int64_t)I * NB + (int64_t)q * NB * lda;
     const int ni = rows_of(I), nq = rows_of(q);
     tile_load(T, 1u, (uint32_t)lda, false, I == q, ni, nq, f);
-    tile_load(T, (uint32_t)lda, 1u, true, false, nq, ni, t);
+    tile_load<PAIRS>(T, (uint32_t)lda, 1u, true, false, nq, ni, t);
   };
   const int T = diag ? nI * (nI + 1) / 2 : nI * nQ;
   It cur{0, 0}, ahead{0, 0};
@@ -1056,8 +1074,13 @@ hipError_t launch_residual(const double* A, int64_t lda, int64_t n, int nrhs, co
   if (part && part_bytes >= residual_part_bytes(n)) {
     int nsup = 0;
     const int S = resid_super(n, &nsup);
-    hipLaunchKernelGGL(k_resid4, dim3((unsigned)((int64_t)nsup * (nsup + 1) / 2)), dim3(256), 0, s,
-                       A, lda, n, nrhs, X, ldx, S, nsup, part);
+    const dim3 grid((unsigned)((int64_t)nsup * (nsup + 1) / 2));
+    if (lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0)
+      hipLaunchKernelGGL(k_resid4<true>, grid, dim3(256), 0, s, A, lda, n, nrhs, X, ldx, S, nsup,
+                         part);
+    else
+      hipLaunchKernelGGL(k_resid4<false>, grid, dim3(256), 0, s, A, lda, n, nrhs, X, ldx, S, nsup,
+                         part);
     hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, n, nrhs,
                        S, nsup, (const double*)part, B, ldb, R, ldr);
     return hipGetLastError();
