@@ -57,6 +57,8 @@ def test_fp64_solve_vs_oracle(M, ctx, n, nrhs):
     ("E4M3", 700, 1.5, 0.0, 4, dict(leaf=64, offdiag=[0], scale_mode=1)),
     ("F16 deep 16rhs", 1024, 1.2, 0.0, 16, dict(leaf=32, offdiag=[1])),
     ("F32 all", 600, 1.05, 0.0, 2, dict(leaf=64, offdiag=[2], leaf_prec=2)),
+    # odd order = odd lda: the residual's transposed reads take the 8-byte path
+    ("F16 odd n", 777, 1.3, 0.0, 3, dict(leaf=64, offdiag=[1])),
 ])
 def test_refined_solution_reaches_fp64(M, ctx, name, n, ratio, shift, nrhs, kw):
     print(f"[gpu] refine {name}", flush=True)
