@@ -2,7 +2,7 @@
 
     python -m paper_2601_08082_amd.studies subkernels [--sizes 8192,16384,...]
     python -m paper_2601_08082_amd.studies depth [--sizes ...] [--max-depth 6]
-    python -m paper_2601_08082_amd.studies step [--sizes 65536] [--steps 3]
+    python -m paper_2601_08082_amd.studies step [--sizes 65536] [--steps 3] [--workload large|single]
 
 subkernels: Tree-SYRK and Tree-TRSM on their own (mpchol_syrk / mpchol_trsm),
 at the shapes the outermost Tree-POTRF level issues for an order-n matrix
@@ -12,9 +12,10 @@ schedule run entirely in its diagonal (last) precision.
 depth: the whole factorization (mpchol_factor) for precision lists of
 increasing depth, [F16] * d + [F32] and [F16] * d + [F64], leaf 256, against
 the all-F32 / all-F64 tree of the same schedule: time, speedup, backward error.
-step: the benchmark's step on its own (factor with [F16,F32,F64] over a leaf
-of 256 in FP64, then the FP64-refined solve of 16 right-hand sides, dominance
-ratio 1.2), a few times, with nothing else in the process: the command a
+step: the benchmark's step on its own (large: factor with [F16,F32,F64] over a
+leaf of 256 in FP64, then the FP64-refined solve of 16 right-hand sides,
+dominance ratio 1.2; single: [F16,F16,F32,F32,F32,F32], 1 right-hand side,
+ratio 1.5), a few times, with nothing else in the process: the command a
 kernel-trace profiler wraps.
 
 Inputs are the synthetic diagonally dominant SPD matrices of the benchmark
@@ -116,15 +117,19 @@ def depth(sizes, max_depth):
     ctx.close()
 
 
-def step(sizes, steps):
+def step(sizes, steps, workload):
     import torch
     from paper_2601_08082_amd import mpchol as M
     from paper_2601_08082_amd import spdgen_gpu
     ctx = M.Context(0)
-    tree = M.Tree(leaf=256, offdiag=[M.F16, M.F32, M.F64], leaf_prec=M.F64)
+    if workload == "large":
+        levels, ratio, nrhs = [M.F16, M.F32, M.F64], 1.2, 16
+    else:
+        levels, ratio, nrhs = [M.F16, M.F16, M.F32, M.F32, M.F32, M.F32], 1.5, 1
+    tree = M.Tree(leaf=256, offdiag=levels, leaf_prec=M.F64)
     for n in sizes:
-        A = spdgen_gpu.gen_spd(n, 1.2, 0.0, seed=8, lda=n)
-        B = spdgen_gpu.gen_rhs(n, 16, seed=108, ldb=n)
+        A = spdgen_gpu.gen_spd(n, ratio, 0.0, seed=8, lda=n)
+        B = spdgen_gpu.gen_rhs(n, nrhs, seed=108, ldb=n)
         L = torch.empty_like(A)
         X = torch.empty_like(B)
         for i in range(steps):
@@ -148,12 +153,13 @@ def main() -> int:
     ap.add_argument("--sizes", default="8192,16384,32768,65536")
     ap.add_argument("--max-depth", type=int, default=6)
     ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--workload", choices=["large", "single"], default="large")
     a = ap.parse_args()
     sizes = [int(x) for x in a.sizes.split(",")]
     if a.study == "subkernels":
         subkernels(sizes)
     elif a.study == "step":
-        step(sizes, a.steps)
+        step(sizes, a.steps, a.workload)
     else:
         depth(sizes, a.max_depth)
     return 0
