@@ -127,7 +127,10 @@ __device__ inline void gemm_d64_tile(double* __restrict__ Lm, int64_t ldl, const
   for (int kt = 0; kt < nk; kt++) {
     gload((kt + 1) * BK, rx, ry);
     __builtin_amdgcn_sched_barrier(0);
+    // this wave's products ahead of the other wave's loads and stores
+    __builtin_amdgcn_s_setprio(1);
     compute(kt & 1);
+    __builtin_amdgcn_s_setprio(0);
     sstore((kt + 1) & 1, rx, ry);
     __syncthreads();
   }
