@@ -324,6 +324,9 @@ __global__ __launch_bounds__(kTrsvThreads, 1) void k_trsv5(int trans, const doub
   __syncthreads();   // the only workgroup-wide barrier
 
   if (w == 4) {
+    // the poller's few instructions go ahead of the compute wave that shares
+    // its SIMD
+    __builtin_amdgcn_s_setprio(2);
     // poller: steps 0 .. (last owned block) in order.  A block this workgroup
     // owns comes from its own chain step through the staging buffer, and the
     // poller publishes it: its stores then wait behind no tile loads (the
