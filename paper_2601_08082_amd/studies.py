@@ -3,6 +3,7 @@
     python -m paper_2601_08082_amd.studies subkernels [--sizes 8192,16384,...]
     python -m paper_2601_08082_amd.studies depth [--sizes ...] [--max-depth 6]
     python -m paper_2601_08082_amd.studies step [--sizes 65536] [--steps 3] [--workload large|single]
+    python -m paper_2601_08082_amd.studies e4m3 [--sizes 32768,65536]
 
 subkernels: Tree-SYRK and Tree-TRSM on their own (mpchol_syrk / mpchol_trsm),
 at the shapes the outermost Tree-POTRF level issues for an order-n matrix
@@ -17,6 +18,11 @@ leaf of 256 in FP64, then the FP64-refined solve of 16 right-hand sides,
 dominance ratio 1.2; single: [F16,F16,F32,F32,F32,F32], 1 right-hand side,
 ratio 1.5), a few times, with nothing else in the process: the command a
 kernel-trace profiler wraps.
+e4m3: the factorization with the level-0 updates in E4M3 (per-block power-of-two
+scales both ways, scale_mode 1) against the same tree with FP16 there,
+[p0, F32, F64] over a leaf of 256 in FP64, dominance ratio 1.2: time, backward
+error, and per launch class the time and rate (the level-0 GEMM class against
+the dense FP8 / FP16 MFMA peak).
 
 Inputs are the synthetic diagonally dominant SPD matrices of the benchmark
 (dominance ratio 1.5) generated on the device; times are the medians of five
@@ -147,9 +153,45 @@ def step(sizes, steps, workload):
     ctx.close()
 
 
+def e4m3(sizes):
+    import torch
+    from paper_2601_08082_amd import mpchol as M
+    from paper_2601_08082_amd import spdgen_gpu
+    peaks = {"gemm_e4m3": 5000.0, "gemm_f16": 2500.0, "gemm_f32": 157.3, "gemm_f64": 78.6}
+    ctx = M.Context(0)
+    for n in sizes:
+        A = spdgen_gpu.gen_spd(n, 1.2, 0.0, 8, n)
+        L = torch.empty_like(A)
+        for p0, sm in ((M.E4M3, 1), (M.F16, 0)):
+            t = M.Tree(leaf=256, offdiag=[p0, M.F32, M.F64], leaf_prec=M.F64, scale_mode=sm)
+            ms = _time(lambda: ctx.factor(A, n, t, L_cm=L)[1]["ms_factor"], reps=3, warm=1)
+            ctx.profile(M.PROF_KINDS)
+            ctx.factor(A, n, t, L_cm=L)
+            torch.cuda.synchronize()
+            prof = ctx.profile_read()
+            ctx.profile([])
+            be = ctx.backward_error(A, L, n)[0] if n <= 32768 else None
+            classes = {}
+            for k, (cms, work, nl) in prof.items():
+                if not nl:
+                    continue
+                rec = {"ms": cms, "launches": nl}
+                if k in peaks and cms > 0:
+                    rec["tflops"] = work / (cms * 1e-3) / 1e12
+                    rec["frac_of_peak"] = rec["tflops"] / peaks[k]
+                classes[k] = rec
+            print(json.dumps({"study": "e4m3", "n": n, "level0": M.PREC_LABELS[p0],
+                              "scale_mode": sm, "ms_factor": ms,
+                              "tflops": n ** 3 / 3 / (ms * 1e-3) / 1e12, "backward_error": be,
+                              "classes": classes}), flush=True)
+        del A, L
+        torch.cuda.empty_cache()
+    ctx.close()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["subkernels", "depth", "step"])
+    ap.add_argument("study", choices=["subkernels", "depth", "step", "e4m3"])
     ap.add_argument("--sizes", default="8192,16384,32768,65536")
     ap.add_argument("--max-depth", type=int, default=6)
     ap.add_argument("--steps", type=int, default=3)
@@ -160,6 +202,8 @@ def main() -> int:
         subkernels(sizes)
     elif a.study == "step":
         step(sizes, a.steps, a.workload)
+    elif a.study == "e4m3":
+        e4m3(sizes)
     else:
         depth(sizes, a.max_depth)
     return 0
